@@ -1,0 +1,525 @@
+/*
+ * spamm_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct FP64 CPU implementation of the Sparse
+ * Approximate Matrix Multiply (SpAMM) and of the dual-channel Newton-Schulz
+ * square-root iteration, written from Challacombe, Haut & Bock, "A N-Body
+ * Solver for Square Root Iteration".  It exists to check the GPU library; it
+ * is never linked into it and shares no code, header or constant with it.
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg call it.
+ *
+ * What it computes, and where the paper defines it:
+ *   - Quadtree Frobenius norms: a node's squared norm is the sum of its four
+ *     children's squared norms (Sec. 1, quadtree norm equation).
+ *   - SpAMM a (x)_tau b (Sec. 2, eq. "newspamm", with the block product as
+ *     the proof of the Proposition in Sec. 2.1 states it): a triple of nodes
+ *     is culled when ||a^i|| ||b^i|| < tau ||a|| ||b|| using the ROOT norms;
+ *     a surviving leaf triple is multiplied densely; otherwise the product
+ *     recurses into the eight child triples.
+ *   - Dual-channel coupled Newton-Schulz (Sec. 3.2, eq. "cannonical") with
+ *     the map h[x] = (3I - x)/2 (alpha = 1), started from y = s/c, z = I.
+ *   - Relative trace error t_k = (n - tr x_k)/n (Sec. 4.2).
+ *   - Tikhonov shift s + mu I (Sec. 6).
+ *
+ * Readings taken where the paper is silent or garbled (each is listed in the
+ * design notes): the lower block row of eq. "newspamm" is printed twice; the
+ * ordinary block product is used.  Culling is strict (<), so ties are kept
+ * and tau = 0 keeps every triple (dense GEMM).  The spectral bound is the
+ * Gershgorin row-sum bound.  Matrices whose order is not a multiple of the
+ * leaf size are zero padded; blocks beyond the padded order up to the next
+ * power of two are virtual zero-norm blocks and never appear in R.
+ *
+ * Parity pins: every function here is checked in the CPU test suite against
+ * something other than itself (NumPy norms and products, brute-force culling,
+ * the Proposition's bound, eigendecomposition, the KMS closed-form inverse,
+ * Higham's sign identity, the scalar spectral recurrence).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_NOT_CONVERGED 1
+#define ORC_STAGNATED 2
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_EDIVERGED (-3)
+
+/* ------------------------------------------------------------------------ */
+/* A padded, row-major FP64 matrix with its quadtree of squared norms.       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;      /* logical order                                          */
+    int64_t b;      /* leaf block order N_b                                   */
+    int64_t nb;     /* leaf blocks per side, ceil(n/b)                        */
+    int64_t np;     /* padded order nb*b                                      */
+    int L;          /* depth of the leaves: 2^L >= nb                          */
+    double *a;      /* np x np, row-major, zero padded                        */
+    double **q;     /* q[d] : (2^d x 2^d) squared norms, row-major, d = 0..L  */
+} qmat;
+
+static int depth_for(int64_t nb) {
+    int L = 0;
+    while (((int64_t)1 << L) < nb) L++;
+    return L;
+}
+
+static void qmat_free(qmat *m) {
+    if (!m) return;
+    free(m->a);
+    if (m->q) {
+        for (int d = 0; d <= m->L; d++) free(m->q[d]);
+        free(m->q);
+    }
+    memset(m, 0, sizeof(*m));
+}
+
+static int qmat_alloc(qmat *m, int64_t n, int64_t b) {
+    memset(m, 0, sizeof(*m));
+    m->n = n;
+    m->b = b;
+    m->nb = (n + b - 1) / b;
+    m->np = m->nb * b;
+    m->L = depth_for(m->nb);
+    m->a = (double *)calloc((size_t)(m->np * m->np), sizeof(double));
+    m->q = (double **)calloc((size_t)(m->L + 1), sizeof(double *));
+    if (!m->a || !m->q) { qmat_free(m); return ORC_ENOMEM; }
+    for (int d = 0; d <= m->L; d++) {
+        int64_t side = (int64_t)1 << d;
+        m->q[d] = (double *)calloc((size_t)(side * side), sizeof(double));
+        if (!m->q[d]) { qmat_free(m); return ORC_ENOMEM; }
+    }
+    return ORC_OK;
+}
+
+/* Quadtree norms (Sec. 1): a leaf's squared Frobenius norm is the running sum
+ * of a_rc^2 over its rows, left to right; a parent's is
+ * (q00 + q01) + (q10 + q11).  Virtual blocks keep q = 0. */
+static void qmat_norms(qmat *m) {
+    const int64_t b = m->b, np = m->np, nb = m->nb;
+    const int L = m->L;
+    const int64_t P = (int64_t)1 << L;
+    memset(m->q[L], 0, (size_t)(P * P) * sizeof(double));
+    for (int64_t i = 0; i < nb; i++)
+        for (int64_t k = 0; k < nb; k++) {
+            double q = 0.0;
+            for (int64_t r = 0; r < b; r++) {
+                const double *row = m->a + (i * b + r) * np + k * b;
+                for (int64_t c = 0; c < b; c++) q += row[c] * row[c];
+            }
+            m->q[L][i * P + k] = q;
+        }
+    for (int d = L - 1; d >= 0; d--) {
+        const int64_t side = (int64_t)1 << d, cs = side * 2;
+        const double *ch = m->q[d + 1];
+        for (int64_t I = 0; I < side; I++)
+            for (int64_t K = 0; K < side; K++) {
+                double q00 = ch[(2 * I) * cs + 2 * K], q01 = ch[(2 * I) * cs + 2 * K + 1];
+                double q10 = ch[(2 * I + 1) * cs + 2 * K], q11 = ch[(2 * I + 1) * cs + 2 * K + 1];
+                m->q[d][I * side + K] = (q00 + q01) + (q10 + q11);
+            }
+    }
+}
+
+static double qmat_root_norm(const qmat *m) { return sqrt(m->q[0][0]); }
+
+/* ------------------------------------------------------------------------ */
+/* SpAMM recursion (Sec. 2, eq. "newspamm").                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const qmat *A, *B;
+    qmat *C;
+    double thr;          /* tau * (||A|| * ||B||), root norms                  */
+    int32_t *triples;    /* optional (i,j,k) records                           */
+    int64_t cap;
+    int64_t count;       /* |R|                                                */
+    unsigned char **want;/* optional: only C nodes flagged here are computed   */
+} spamm_job;
+
+/* Recursion levels above this depth run their C quadrants as OpenMP tasks. */
+#define TASK_DEPTH 3
+
+/* Dense leaf product C_ij += A_ik B_kj (plain triple loop). */
+static void leaf_gemm(const qmat *A, const qmat *B, qmat *C, int64_t i, int64_t j, int64_t k) {
+    const int64_t b = A->b, np = A->np;
+    for (int64_t r = 0; r < b; r++) {
+        double *crow = C->a + (i * b + r) * np + j * b;
+        const double *arow = A->a + (i * b + r) * np + k * b;
+        for (int64_t l = 0; l < b; l++) {
+            const double av = arow[l];
+            const double *brow = B->a + (k * b + l) * np + j * b;
+            for (int64_t c = 0; c < b; c++) crow[c] += av * brow[c];
+        }
+    }
+}
+
+/* One node triple: A node (I,K) times B node (K,J) at depth d, contributing to
+ * C node (I,J).  Culled when the product of the two node norms is strictly
+ * below the threshold; at the leaves the survivors are multiplied; otherwise
+ * each C quadrant (ci,cj) receives A(ci,0) B(0,cj) then A(ci,1) B(1,cj). */
+static void spamm_rec(spamm_job *job, int d, int64_t I, int64_t J, int64_t K) {
+    const qmat *A = job->A, *B = job->B;
+    const int64_t side = (int64_t)1 << d;
+    const double na = sqrt(A->q[d][I * side + K]);
+    const double nb = sqrt(B->q[d][K * side + J]);
+    if (na * nb < job->thr) return;
+    if (d == A->L) {
+        if (I >= A->nb || J >= A->nb || K >= A->nb) return; /* virtual block */
+        if (job->want && !job->want[A->L][I * side + J]) return;
+        leaf_gemm(A, B, job->C, I, J, K);
+        int64_t idx;
+#pragma omp atomic capture
+        idx = job->count++;
+        if (job->triples && idx < job->cap) {
+            job->triples[3 * idx + 0] = (int32_t)I;
+            job->triples[3 * idx + 1] = (int32_t)J;
+            job->triples[3 * idx + 2] = (int32_t)K;
+        }
+        return;
+    }
+    /* The four C quadrants are independent; inside each one the two k-halves
+     * run in order, so every C leaf accumulates its k in increasing order
+     * whether or not the quadrants run as parallel tasks. */
+    for (int ci = 0; ci < 2; ci++)
+        for (int cj = 0; cj < 2; cj++) {
+            const int64_t CI = 2 * I + ci, CJ = 2 * J + cj;
+            if (job->want && !job->want[d + 1][CI * (2 * side) + CJ]) continue;
+#pragma omp task if (d < TASK_DEPTH) firstprivate(CI, CJ)
+            {
+                spamm_rec(job, d + 1, CI, CJ, 2 * K);
+                spamm_rec(job, d + 1, CI, CJ, 2 * K + 1);
+            }
+        }
+#pragma omp taskwait
+}
+
+/* C = A (x)_tau B.  C must be allocated with the same geometry; it is zeroed
+ * here and its norms are rebuilt afterwards.  Returns |R|. */
+static int64_t spamm(const qmat *A, const qmat *B, qmat *C, double tau, int32_t *triples, int64_t cap) {
+    spamm_job job;
+    job.A = A;
+    job.B = B;
+    job.C = C;
+    job.thr = tau * (qmat_root_norm(A) * qmat_root_norm(B));
+    job.triples = triples;
+    job.cap = cap;
+    job.count = 0;
+    job.want = NULL;
+    memset(C->a, 0, (size_t)(C->np * C->np) * sizeof(double));
+#pragma omp parallel
+#pragma omp single
+    spamm_rec(&job, 0, 0, 0, 0);
+    qmat_norms(C);
+    return job.count;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported: norms and one product.                                          */
+/* ------------------------------------------------------------------------ */
+
+int64_t oracle_pyramid_len(int64_t n, int64_t b) {
+    int L = depth_for((n + b - 1) / b);
+    return (((int64_t)1 << (2 * (L + 1))) - 1) / 3;
+}
+
+static void load_padded(qmat *m, const double *src, int64_t n) {
+    for (int64_t r = 0; r < n; r++) memcpy(m->a + r * m->np, src + r * n, (size_t)n * sizeof(double));
+}
+
+static void store_logical(const qmat *m, double *dst, int64_t n) {
+    for (int64_t r = 0; r < n; r++) memcpy(dst + r * n, m->a + r * m->np, (size_t)n * sizeof(double));
+}
+
+/* Norm pyramid of a dense n x n row-major matrix: levels from the leaves
+ * (2^L x 2^L, zero padded) up to the root, as NORMS (square roots of the
+ * summed squares).  pyr must hold oracle_pyramid_len(n,b) doubles. */
+int oracle_norms(const double *a, int64_t n, int64_t b, double *pyr) {
+    if (n <= 0 || b <= 0) return ORC_EINVAL;
+    qmat m;
+    if (qmat_alloc(&m, n, b)) return ORC_ENOMEM;
+    load_padded(&m, a, n);
+    qmat_norms(&m);
+    int64_t off = 0;
+    for (int d = m.L; d >= 0; d--) {
+        int64_t cnt = (int64_t)1 << (2 * d);
+        for (int64_t t = 0; t < cnt; t++) pyr[off + t] = sqrt(m.q[d][t]);
+        off += cnt;
+    }
+    qmat_free(&m);
+    return ORC_OK;
+}
+
+/* C = A (x)_tau B for dense n x n row-major A, B.  triples (optional) receives
+ * up to cap (i,j,k) records in recursion order; *count receives |R|. */
+int oracle_spamm(const double *a, const double *b_, double *c, int64_t n, int64_t b, double tau,
+                 int32_t *triples, int64_t cap, int64_t *count) {
+    if (n <= 0 || b <= 0 || !(tau >= 0.0)) return ORC_EINVAL;
+    qmat A, B, C;
+    if (qmat_alloc(&A, n, b)) return ORC_ENOMEM;
+    if (qmat_alloc(&B, n, b)) { qmat_free(&A); return ORC_ENOMEM; }
+    if (qmat_alloc(&C, n, b)) { qmat_free(&A); qmat_free(&B); return ORC_ENOMEM; }
+    load_padded(&A, a, n);
+    load_padded(&B, b_, n);
+    qmat_norms(&A);
+    qmat_norms(&B);
+    int64_t cnt = spamm(&A, &B, &C, tau, triples, cap);
+    store_logical(&C, c, n);
+    if (count) *count = cnt;
+    qmat_free(&A);
+    qmat_free(&B);
+    qmat_free(&C);
+    return ORC_OK;
+}
+
+/* Sampled product: only the C leaf tiles listed in tiles[2*t], tiles[2*t+1]
+ * (t < ntiles) are computed, by the same recursion restricted to the C nodes
+ * that contain a listed tile.  Each listed tile is written to
+ * out[t*b*b ...] (b x b, row-major, padding included).  Used to check
+ * products too large for the full oracle one tile at a time.  counts[t]
+ * receives |R_ij| of the listed tile. */
+int oracle_spamm_tiles(const double *a, const double *b_, int64_t n, int64_t b, double tau, const int32_t *tiles,
+                       int64_t ntiles, double *out, int64_t *counts) {
+    if (n <= 0 || b <= 0 || !(tau >= 0.0) || ntiles < 0) return ORC_EINVAL;
+    qmat A, B, C;
+    if (qmat_alloc(&A, n, b)) return ORC_ENOMEM;
+    if (qmat_alloc(&B, n, b)) { qmat_free(&A); return ORC_ENOMEM; }
+    if (qmat_alloc(&C, n, b)) { qmat_free(&A); qmat_free(&B); return ORC_ENOMEM; }
+    load_padded(&A, a, n);
+    load_padded(&B, b_, n);
+    qmat_norms(&A);
+    qmat_norms(&B);
+    const int L = A.L;
+    unsigned char **want = (unsigned char **)calloc((size_t)(L + 1), sizeof(unsigned char *));
+    int st = ORC_OK;
+    for (int d = 0; d <= L && want; d++) {
+        want[d] = (unsigned char *)calloc((size_t)1 << (2 * d), 1);
+        if (!want[d]) st = ORC_ENOMEM;
+    }
+    if (!want) st = ORC_ENOMEM;
+    for (int64_t t = 0; t < ntiles && st == ORC_OK; t++) {
+        int64_t i = tiles[2 * t], j = tiles[2 * t + 1];
+        if (i < 0 || j < 0 || i >= A.nb || j >= A.nb) { st = ORC_EINVAL; break; }
+        for (int d = L; d >= 0; d--) {
+            int64_t sh = L - d;
+            want[d][(i >> sh) * ((int64_t)1 << d) + (j >> sh)] = 1;
+        }
+    }
+    if (st == ORC_OK) {
+        spamm_job job;
+        job.A = &A;
+        job.B = &B;
+        job.C = &C;
+        job.thr = tau * (qmat_root_norm(&A) * qmat_root_norm(&B));
+        job.cap = ntiles * A.nb;
+        job.triples = (int32_t *)malloc((size_t)(3 * job.cap + 3) * sizeof(int32_t));
+        job.count = 0;
+        job.want = want;
+        if (!job.triples) st = ORC_ENOMEM;
+        if (st == ORC_OK) {
+#pragma omp parallel
+#pragma omp single
+            spamm_rec(&job, 0, 0, 0, 0);
+            for (int64_t t = 0; t < ntiles; t++) {
+                int64_t i = tiles[2 * t], j = tiles[2 * t + 1];
+                for (int64_t r = 0; r < b; r++)
+                    memcpy(out + t * b * b + r * b, C.a + (i * b + r) * C.np + j * b, (size_t)b * sizeof(double));
+                if (counts) {
+                    int64_t cnt = 0;
+                    for (int64_t e = 0; e < job.count && e < job.cap; e++)
+                        if (job.triples[3 * e] == i && job.triples[3 * e + 1] == j) cnt++;
+                    counts[t] = cnt;
+                }
+            }
+        }
+        free(job.triples);
+    }
+    if (want) {
+        for (int d = 0; d <= L; d++) free(want[d]);
+        free(want);
+    }
+    qmat_free(&A);
+    qmat_free(&B);
+    qmat_free(&C);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dual-channel Newton-Schulz square root (Sec. 3.2, eq. "cannonical").       */
+/* ------------------------------------------------------------------------ */
+
+/* Gershgorin bound max_i sum_j |s_ij|, rows summed left to right. */
+static double gershgorin(const double *s, int64_t n) {
+    double c = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double r = 0.0;
+        for (int64_t j = 0; j < n; j++) r += fabs(s[i * n + j]);
+        if (r > c) c = r;
+    }
+    return c;
+}
+
+/* Input checks: finite entries and symmetry max|s - s^T| <= 1e-14 max|s|. */
+static int check_input(const double *s, int64_t n) {
+    double amax = 0.0, dmax = 0.0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < n; j++) {
+            double v = s[i * n + j];
+            if (!isfinite(v)) return ORC_EINVAL;
+            if (fabs(v) > amax) amax = fabs(v);
+            double d = fabs(v - s[j * n + i]);
+            if (d > dmax) dmax = d;
+        }
+    if (dmax > 1e-14 * amax) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/* One dual-channel update (Sec. 3.2, eq. "cannonical", alpha = 1): x holds
+ * x_k = y_k (x)_tau z_k on entry and h_k = 1.5 I_n - 0.5 x_k on exit;
+ * yn = h_k (x)_{tau_s} y_k, zn = z_k (x)_tau h_k. */
+static void ns_update(qmat *x, const qmat *y, const qmat *z, qmat *yn, qmat *zn, double tau, double tau_s,
+                      int64_t *ny, int64_t *nz) {
+    const int64_t n = x->n, np = x->np;
+    for (int64_t i = 0; i < np; i++)
+        for (int64_t j = 0; j < np; j++) {
+            const double v = x->a[i * np + j];
+            x->a[i * np + j] = ((i == j && i < n) ? 1.5 : 0.0) - 0.5 * v;
+        }
+    qmat_norms(x);
+    *ny = spamm(x, y, yn, tau_s, NULL, 0);
+    *nz = spamm(z, x, zn, tau, NULL, 0);
+}
+
+/* One update from an arbitrary (y, z) pair of dense n x n matrices, for the
+ * fixed-point derivative check: x = y (x)_tau z, then yn, zn as above. */
+int oracle_ns_step(const double *y_in, const double *z_in, double *y_out, double *z_out, int64_t n, int64_t b,
+                   double tau, double tau_s) {
+    if (n <= 0 || b <= 0 || !(tau >= 0.0)) return ORC_EINVAL;
+    if (tau_s < 0.0) tau_s = tau;
+    qmat y, z, x, yn, zn;
+    int ok = qmat_alloc(&y, n, b) == 0;
+    ok = ok && qmat_alloc(&z, n, b) == 0;
+    ok = ok && qmat_alloc(&x, n, b) == 0;
+    ok = ok && qmat_alloc(&yn, n, b) == 0;
+    ok = ok && qmat_alloc(&zn, n, b) == 0;
+    if (!ok) return ORC_ENOMEM;
+    load_padded(&y, y_in, n);
+    load_padded(&z, z_in, n);
+    qmat_norms(&y);
+    qmat_norms(&z);
+    int64_t ny, nz;
+    spamm(&y, &z, &x, tau, NULL, 0);
+    ns_update(&x, &y, &z, &yn, &zn, tau, tau_s, &ny, &nz);
+    store_logical(&yn, y_out, n);
+    store_logical(&zn, z_out, n);
+    qmat_free(&y);
+    qmat_free(&z);
+    qmat_free(&x);
+    qmat_free(&yn);
+    qmat_free(&zn);
+    return ORC_OK;
+}
+
+/*
+ * oracle_ns_sqrt: y -> s^{1/2}, z -> s^{-1/2}.
+ *
+ *   s' = (s + mu_rel*c0*I)/c with c0, c Gershgorin bounds of s and of the
+ *   shifted matrix; y_0 = s', z_0 = I_n.  For k = 0, 1, ...:
+ *     x_k = y_k (x)_tau z_k;  r_k = ||I_n - x_k||_F;  t_k = (n - tr x_k)/n
+ *     r_k < tol                       -> OK, return (y_k, z_k)
+ *     r_k not finite or
+ *       r_k > 10 max(r_0, sqrt(n))    -> DIVERGED
+ *     stagnation_stop and r_k >= .99 r_{k-1} >= .99^2 r_{k-2}... (two
+ *       consecutive non-decreases by 1%) -> STAGNATED (outputs valid)
+ *     k == maxit                      -> NOT_CONVERGED (outputs valid)
+ *     h_k = (3 I_n - x_k)/2 ;  y_{k+1} = h_k (x)_{tau_s} y_k ;
+ *     z_{k+1} = z_k (x)_tau h_k
+ *   Returned: Y = sqrt(c) y_k, Z = z_k / sqrt(c) (logical n x n).
+ *
+ * Histories (optional, capacity maxit+1 entries): r_hist[k], t_hist[k],
+ * nR_hist[3k..3k+2] = |R| of x_k, y_{k+1}, z_{k+1} (the last two 0 when no
+ * update followed).  *iters = number of (y, z) updates performed.
+ */
+int oracle_ns_sqrt(const double *s, double *Y, double *Z, int64_t n, int64_t b, double tau, double tau_s,
+                   double tol, int maxit, double mu_rel, int stagnation_stop, double *r_hist, double *t_hist,
+                   int64_t *nR_hist, int *iters, double *scale) {
+    if (n <= 0 || b <= 0 || !(tau >= 0.0) || !(tol > 0.0) || maxit < 0 || !(mu_rel >= 0.0)) return ORC_EINVAL;
+    if (tau_s < 0.0) tau_s = tau;
+    int st = check_input(s, n);
+    if (st) return st;
+
+    double *sw = (double *)malloc((size_t)(n * n) * sizeof(double));
+    if (!sw) return ORC_ENOMEM;
+    memcpy(sw, s, (size_t)(n * n) * sizeof(double));
+    if (mu_rel > 0.0) {
+        const double mu = mu_rel * gershgorin(sw, n);
+        for (int64_t i = 0; i < n; i++) sw[i * n + i] += mu;
+    }
+    const double c = gershgorin(sw, n);
+    if (!(c > 0.0)) { free(sw); return ORC_EINVAL; }
+
+    qmat y, z, x, yn, zn;
+    int ok = qmat_alloc(&y, n, b) == 0;
+    ok = ok && qmat_alloc(&z, n, b) == 0;
+    ok = ok && qmat_alloc(&x, n, b) == 0;
+    ok = ok && qmat_alloc(&yn, n, b) == 0;
+    ok = ok && qmat_alloc(&zn, n, b) == 0;
+    if (!ok) { free(sw); return ORC_ENOMEM; }
+    const int64_t np = y.np;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < n; j++) y.a[i * np + j] = sw[i * n + j] / c;
+    free(sw);
+    for (int64_t i = 0; i < n; i++) z.a[i * np + i] = 1.0;
+    qmat_norms(&y);
+    qmat_norms(&z);
+
+    int status = ORC_NOT_CONVERGED;
+    int k = 0;
+    double r0 = 0.0, r_prev = 0.0;
+    int nondecrease = 0;
+    for (k = 0;; k++) {
+        int64_t nx = spamm(&y, &z, &x, tau, NULL, 0);
+        /* r_k and the trace over the logical block */
+        double r2 = 0.0, tr = 0.0;
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t j = 0; j < n; j++) {
+                const double v = x.a[i * np + j];
+                const double e = (i == j ? 1.0 : 0.0) - v;
+                r2 += e * e;
+                if (i == j) tr += v;
+            }
+        const double r = sqrt(r2);
+        const double t = ((double)n - tr) / (double)n;
+        if (r_hist) r_hist[k] = r;
+        if (t_hist) t_hist[k] = t;
+        if (nR_hist) { nR_hist[3 * k] = nx; nR_hist[3 * k + 1] = 0; nR_hist[3 * k + 2] = 0; }
+        if (k == 0) r0 = r;
+        if (r < tol) { status = ORC_OK; break; }
+        if (!isfinite(r) || r > 10.0 * fmax(r0, sqrt((double)n))) { status = ORC_EDIVERGED; break; }
+        if (stagnation_stop && k > 0) {
+            nondecrease = (r >= 0.99 * r_prev) ? nondecrease + 1 : 0;
+            if (nondecrease >= 2) { status = ORC_STAGNATED; break; }
+        }
+        r_prev = r;
+        if (k == maxit) { status = ORC_NOT_CONVERGED; break; }
+        int64_t ny, nz;
+        ns_update(&x, &y, &z, &yn, &zn, tau, tau_s, &ny, &nz);
+        if (nR_hist) { nR_hist[3 * k + 1] = ny; nR_hist[3 * k + 2] = nz; }
+        qmat tmp = y; y = yn; yn = tmp;
+        tmp = z; z = zn; zn = tmp;
+    }
+    const double sc = sqrt(c);
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < n; j++) {
+            Y[i * n + j] = y.a[i * np + j] * sc;
+            Z[i * n + j] = z.a[i * np + j] / sc;
+        }
+    if (iters) *iters = k;
+    if (scale) *scale = c;
+    qmat_free(&y);
+    qmat_free(&z);
+    qmat_free(&x);
+    qmat_free(&yn);
+    qmat_free(&zn);
+    return status;
+}
