@@ -1,0 +1,180 @@
+/*
+ * spamm.h -- C ABI of the MI355X (gfx950) SpAMM / Newton-Schulz library.
+ *
+ * Implements the Sparse Approximate Matrix Multiply a (x)_tau b of
+ * Challacombe, Haut & Bock, "A N-Body Solver for Square Root Iteration"
+ * (Sec. 2, eq. "newspamm", error bound of Sec. 2.1) and the dual-channel
+ * coupled Newton-Schulz iteration for s^{1/2} and s^{-1/2} built on it
+ * (Sec. 3.2, eq. "cannonical").
+ *
+ * Conventions shared by every entry point:
+ *   - Matrix arguments are DEVICE pointers owned by the caller: square, FP64,
+ *     row-major with leading dimension ld >= n.  The library never frees or
+ *     retains them past the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  Work is enqueued on it; every entry point that returns host
+ *     values (statistics, results, statuses) synchronises that stream before
+ *     returning, so outputs are complete when the call returns.
+ *   - Return value: a spamm_status.  0 = success; > 0 = warning with valid
+ *     outputs; < 0 = error, outputs undefined, text in spamm_last_error().
+ *   - Invalid arguments (n <= 0, ld < n, tau < 0 or NaN, tol <= 0, maxit < 0,
+ *     leaf not in {16, 32, 64}, an unknown precision, a NULL required pointer)
+ *     return SPAMM_EINVAL before any work is enqueued.
+ *   - A context owns all scratch memory (tiles, norm pyramids, task lists).
+ *     Use one context per host thread; calls on one context are not
+ *     thread-safe.  Scratch grows on demand and is reused across calls.
+ *   - Leaf block order: the paper's N_b; n need not be a multiple of it
+ *     (zero padding, outside the logical identity).
+ */
+#ifndef SPAMM_H
+#define SPAMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPAMM_OK = 0,
+    SPAMM_NOT_CONVERGED = 1, /* maxit updates done without r < tol; outputs = last iterate     */
+    SPAMM_STAGNATED = 2,     /* opt-in stagnation stop fired; outputs = last iterate           */
+    SPAMM_EINVAL = -1,       /* invalid argument or input (NaN/Inf, asymmetric s)              */
+    SPAMM_ENOMEM = -2,       /* device or pinned allocation failed                             */
+    SPAMM_EDIVERGED = -3,    /* r_k not finite or r_k > 10 max(r_0, sqrt(n))                   */
+    SPAMM_EHIP = -4,         /* a HIP runtime call failed                                      */
+    SPAMM_ECAPACITY = -5     /* caller's triple buffer too small (stats still filled)          */
+} spamm_status;
+
+/* Arithmetic of the leaf products.  Norms, the cull decision, the Newton-
+ * Schulz residual and trace are FP64 in every mode; norms are taken of the
+ * values as stored in the leaf precision. */
+typedef enum {
+    SPAMM_F64 = 0,    /* FP64 tiles, FP64 MFMA                                       */
+    SPAMM_F32 = 1,    /* FP32 tiles, FP32 MFMA, FP32 accumulation                    */
+    SPAMM_BF16X3 = 2  /* FP32 tiles; each product a_hi b_hi + a_hi b_lo + a_lo b_hi
+                         on BF16 MFMA with FP32 accumulation (a = a_hi + a_lo)       */
+} spamm_prec;
+
+typedef struct spamm_ctx spamm_ctx;
+
+/* Create a context on HIP device `device` (made current for the calls made
+ * through this context).  *ctx receives the handle.  Errors: EINVAL (NULL
+ * ctx or bad device), EHIP. */
+int spamm_create(spamm_ctx **ctx, int device);
+
+/* Release the context and all its device memory (synchronises the device). */
+int spamm_destroy(spamm_ctx *ctx);
+
+/* Thread-local text describing the most recent status < 0 on this thread. */
+const char *spamm_last_error(void);
+
+/* Number of entries of a norm pyramid for order n and leaf b:
+ * (4^(L+1) - 1)/3 with L = ceil(log2(ceil(n/b))).  Returns -1 on bad args. */
+int64_t spamm_pyramid_len(int64_t n, int leaf);
+
+/*
+ * Frobenius-norm quadtree of A (Sec. 1, quadtree norm equation): the squared
+ * norm of a node is the sum of its four children's squared norms, summed as
+ * (q00 + q01) + (q10 + q11); leaves are the b x b blocks.
+ *
+ * pyramid: DEVICE, spamm_pyramid_len(n, leaf) doubles, receives NORMS (square
+ *   roots), leaves first: the leaf level is 2^L x 2^L row-major (blocks past
+ *   ceil(n/b), the virtual blocks of the padded tree, are 0), then each parent
+ *   level up to the root (one value).
+ * root_norm_host: optional HOST double, receives ||A||_F (synchronises).
+ */
+int spamm_norms(spamm_ctx *ctx, const double *A, int64_t n, int64_t ld, int leaf, double *pyramid,
+                double *root_norm_host, void *stream);
+
+typedef struct {
+    int64_t retained; /* |R|, retained leaf triples                          */
+    int64_t possible; /* ceil(n/b)^3                                         */
+    double thr;       /* tau * (||A|| * ||B||)                               */
+    double flops;     /* 2 b^3 |R|                                           */
+} spamm_stats;
+
+/*
+ * C = A (x)_tau B (Sec. 2, eq. "newspamm"): every leaf triple (i,j,k) with
+ * ||A_ik|| * ||B_kj|| < tau * (||A|| * ||B||) is culled (strict <, so tau = 0
+ * keeps all and is the dense product); each C block accumulates its retained
+ * k in increasing order.  The retained set equals the paper's recursive one
+ * because parent norms bound child norms.  ||C - A B||_F <= n^2 tau ||A|| ||B||
+ * (Sec. 2.1).
+ *
+ * A, B: DEVICE inputs; C: DEVICE output (n x n, same ld; may not alias A/B).
+ * prec: a spamm_prec.  triples: optional DEVICE int32[cap][3] receiving the
+ *   retained (i,j,k) sorted lexicographically; SPAMM_ECAPACITY if |R| > cap
+ *   (C and stats are still valid).  stats: optional HOST output.
+ * Synchronises the stream when stats or triples are requested.
+ */
+int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, int64_t n, int64_t ld,
+                   double tau, int leaf, int prec, int32_t *triples, int64_t cap, spamm_stats *stats,
+                   void *stream);
+
+typedef struct {
+    int leaf;            /* N_b in {16, 32, 64}; 0 = 32                                    */
+    int prec;            /* spamm_prec                                                     */
+    double tau_s;        /* threshold of the y channel h (x) y; < 0 = tau (Sec. 4.1)         */
+    double mu_rel;       /* Tikhonov shift s + mu_rel * c0 * I, c0 the Gershgorin bound of s
+                            (Sec. 6); 0 = none                                             */
+    int stagnation_stop; /* 1 = stop when r_k >= 0.99 r_{k-1} twice in a row              */
+} spamm_ns_opts;
+
+typedef struct {
+    int iterations;        /* (y, z) updates performed                                  */
+    double resid;          /* last in-loop r_k = ||I_n - y_k (x)_tau z_k||_F             */
+    double trace_err;      /* last t_k = (n - tr x_k)/n (Sec. 4.2)                       */
+    double scale;          /* c, the Gershgorin bound used to scale s                    */
+    int64_t triples_total; /* sum of |R| over all products                               */
+    double flops_total;    /* 2 b^3 triples_total                                        */
+} spamm_ns_result;
+
+/*
+ * Dual-channel coupled Newton-Schulz (Sec. 3.2, eq. "cannonical") with the map
+ * h[x] = (3 I - x)/2.  s' = (s + mu I)/c with c = max_i sum_j |s_ij| (a bound
+ * on the largest eigenvalue, so the spectrum lies in (0, 1]); y_0 = s',
+ * z_0 = I_n.  For k = 0, 1, ...: x_k = y_k (x)_tau z_k; r_k = ||I_n - x_k||_F;
+ * stop with OK when r_k < tol, EDIVERGED when r_k is not finite or exceeds
+ * 10 max(r_0, sqrt(n)), STAGNATED (opt-in) after two consecutive
+ * r_k >= 0.99 r_{k-1}, NOT_CONVERGED when k == maxit; otherwise
+ * h_k = 1.5 I_n - 0.5 x_k, y_{k+1} = h_k (x)_{tau_s} y_k, z_{k+1} = z_k (x)_tau h_k.
+ *
+ * s: DEVICE input, symmetric (max|s - s^T| <= 1e-14 max|s|) and finite, else
+ *   EINVAL.  Y ~ s^{1/2} = sqrt(c) y_k and Z ~ s^{-1/2} = z_k / sqrt(c):
+ *   DEVICE outputs with leading dimension ld.  opts: NULL = defaults (leaf 32,
+ *   F64, tau_s = tau, no shift, literal stop rule).  res: optional HOST output.
+ * Synchronises the stream once per iteration (the stop test) and at the end.
+ */
+int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, int64_t ld, double tau,
+            double tol, int maxit, const spamm_ns_opts *opts, spamm_ns_result *res, void *stream);
+
+/* Per-iteration record of the most recent ns_sqrt on this context, HOST
+ * outputs of capacity cap entries: r[k], t[k] and nR[3k..3k+2] = |R| of x_k,
+ * y_{k+1}, z_{k+1} (the last two are 0 where no update followed).  Returns the
+ * number of entries available (iterations + 1), or < 0 on error. */
+int spamm_ns_history(spamm_ctx *ctx, double *r, double *t, int64_t *nR, int cap);
+
+/* Launch timing, for measurement.  While enabled, every leaf-product launch
+ * (kind 0), cull launch (kind 1) and norm-pyramid launch (kind 2) enqueued
+ * through this context is bracketed by a pair of HIP events recorded on the
+ * same stream.  Events come from a fixed pool created at enable time (no
+ * allocation while solving); when it is exhausted recording stops silently.
+ * spamm_profile_enable(ctx, 1) also clears earlier records; 0 disables. */
+int spamm_profile_enable(spamm_ctx *ctx, int enable);
+
+/* Durations in milliseconds of the recorded launches of `kind`, in launch
+ * order, into HOST ms[cap].  Returns the number recorded (may exceed cap), or
+ * < 0 on error.  The recorded work must be complete (every entry point that
+ * reports results has synchronised its stream).  Clears nothing. */
+int spamm_profile_read(spamm_ctx *ctx, int kind, double *ms, int cap);
+
+/* Forget the recorded launches (the pool is reused). */
+int spamm_profile_reset(spamm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPAMM_H */

@@ -1,0 +1,717 @@
+// HIP kernels for gfx950 (CDNA4): input checks and ingest, the Frobenius-norm
+// pyramid, the two-sided cull, the leaf products on MFMA with the fused
+// Newton-Schulz epilogue, reductions and egress.
+//
+// Layout in HBM: every operand is tile-major, b x b tiles each contiguous and
+// row-major inside, tile (i,k) at offset (i*nb + k)*b*b.  The pyramid holds
+// squared norms, leaves first (P x P, P = 2^L >= nb), then each parent level.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace spk {
+
+Geom make_geom(int64_t n, int b) {
+    Geom g;
+    g.n = n;
+    g.b = b;
+    g.nb = (int)((n + b - 1) / b);
+    g.L = 0;
+    while ((1 << g.L) < g.nb) g.L++;
+    g.P = 1 << g.L;
+    return g;
+}
+
+int64_t pyr_len(int P) {
+    int64_t s = 0;
+    for (int64_t S = P; S >= 1; S >>= 1) s += S * S;
+    return s;
+}
+
+int64_t level_off(int P, int S) {
+    int64_t o = 0;
+    for (int64_t T = P; T > S; T >>= 1) o += T * T;
+    return o;
+}
+
+__device__ inline int64_t dev_level_off(int P, int S) {
+    int64_t o = 0;
+    for (int64_t T = P; T > S; T >>= 1) o += T * T;
+    return o;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block-wide sum in a fixed order: lanes by xor-butterfly, then waves 0..W-1.
+template <int NT>
+__device__ inline double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / 64; ++i) t += sh[i];
+    return t;  // valid in thread 0
+}
+
+template <int NT>
+__device__ inline double block_max(double v, double *sh) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / 64; ++i) t = fmax(t, sh[i]);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Input checks: max |s - s^T|, max |s|, and a non-finite flag, per 32x32 block
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_check_input(const double *__restrict__ s, int64_t n, int64_t ld,
+                                                      double *__restrict__ part) {
+    __shared__ double tileT[32][33];
+    __shared__ double sh[4];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    // the mirrored block s[c0.., r0..], stored transposed
+    for (int m = 0; m < 32; m += 8) {
+        const int64_t r = c0 + ty + m, c = r0 + tx;
+        tileT[tx][ty + m] = (r < n && c < n) ? s[r * ld + c] : 0.0;
+    }
+    __syncthreads();
+    double dmax = 0.0, amax = 0.0, bad = 0.0;
+    for (int m = 0; m < 32; m += 8) {
+        const int64_t r = r0 + ty + m, c = c0 + tx;
+        if (r < n && c < n) {
+            const double v = s[r * ld + c];
+            if (!isfinite(v)) bad = 1.0;
+            amax = fmax(amax, fabs(v));
+            const double d = fabs(v - tileT[ty + m][tx]);
+            dmax = fmax(dmax, d);
+        }
+    }
+    dmax = block_max<256>(dmax, sh);
+    amax = block_max<256>(amax, sh);
+    bad = block_max<256>(bad, sh);
+    if (threadIdx.x == 0) {
+        const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        part[3 * b + 0] = dmax;
+        part[3 * b + 1] = amax;
+        part[3 * b + 2] = bad;
+    }
+}
+
+// Max over `count` strided entries (stride, offset), single block.
+__global__ __launch_bounds__(1024) void k_reduce_max(const double *__restrict__ x, int64_t count, int stride,
+                                                      int offset, double *__restrict__ out) {
+    __shared__ double sh[16];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 1024) m = fmax(m, x[i * stride + offset]);
+    m = block_max<1024>(m, sh);
+    if (threadIdx.x == 0) *out = m;
+}
+
+hipError_t launch_check_input(const double *s, int64_t n, int64_t ld, double *part, double *out3,
+                              hipStream_t st) {
+    const int nbk = (int)((n + 31) / 32);
+    hipLaunchKernelGGL(k_check_input, dim3(nbk, nbk), dim3(256), 0, st, s, n, ld, part);
+    for (int c = 0; c < 3; ++c)
+        hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(1024), 0, st, part, (int64_t)nbk * nbk, 3, c, out3 + c);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gershgorin bound: column j sums |s_ij + [i==j] mu| over i = 0..n-1 in order.
+// For an exactly symmetric s this is the row sum taken left to right.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_colsum(const double *__restrict__ s, int64_t n, int64_t ld, double mu,
+                                                double *__restrict__ colsum) {
+    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (j >= n) return;
+    // The sum stays strictly sequential in i; the loads of a group of U rows
+    // are issued together so that enough memory requests are in flight.
+    constexpr int U = 16;
+    double acc = 0.0;
+    int64_t i = 0;
+    for (; i + U <= n; i += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = s[(i + u) * ld + j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double x = v[u];
+            if (i + u == j) x = x + mu;
+            acc += fabs(x);
+        }
+    }
+    for (; i < n; ++i) {
+        double x = s[i * ld + j];
+        if (i == j) x = x + mu;
+        acc += fabs(x);
+    }
+    colsum[j] = acc;
+}
+
+hipError_t launch_colsum_max(const double *s, int64_t n, int64_t ld, double mu, double *colsum, double *out1,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, s, n, ld, mu, colsum);
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(1024), 0, st, colsum, n, 1, 0, out1);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ingest: s' = (s + mu I)/c into tile-major storage of type T, zero padded,
+// with each tile's squared norm taken of the stored values.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ingest(const double *__restrict__ s, int64_t ld, double mu, double c,
+                                                 Geom g, T *__restrict__ tiles, double *__restrict__ qleaf) {
+    __shared__ double sh[4];
+    const int t = blockIdx.x;
+    const int i = t / g.nb, k = t % g.nb;
+    const int b = g.b;
+    T *dst = tiles + (int64_t)t * b * b;
+    double q = 0.0;
+    for (int e = threadIdx.x; e < b * b; e += 256) {
+        const int r = e / b, cc = e % b;
+        const int64_t gi = (int64_t)i * b + r, gj = (int64_t)k * b + cc;
+        double v = 0.0;
+        if (gi < g.n && gj < g.n) {
+            v = s[gi * ld + gj];
+            if (gi == gj) v = v + mu;
+            v = v / c;
+        }
+        const T tv = (T)v;
+        dst[e] = tv;
+        const double dv = (double)tv;
+        q += dv * dv;
+    }
+    q = block_sum<256>(q, sh);
+    if (threadIdx.x == 0) qleaf[(int64_t)i * g.P + k] = q;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_identity(Geom g, T *__restrict__ tiles, double *__restrict__ qleaf) {
+    const int t = blockIdx.x;
+    const int i = t / g.nb, k = t % g.nb;
+    const int b = g.b;
+    T *dst = tiles + (int64_t)t * b * b;
+    for (int e = threadIdx.x; e < b * b; e += 256) {
+        const int r = e / b, cc = e % b;
+        const int64_t gi = (int64_t)i * b + r, gj = (int64_t)k * b + cc;
+        dst[e] = (T)((gi == gj && gi < g.n) ? 1.0 : 0.0);
+    }
+    if (threadIdx.x == 0) {
+        int64_t ones = 0;
+        if (i == k) {
+            const int64_t lo = (int64_t)i * b, hi = lo + b < g.n ? lo + b : g.n;
+            ones = hi > lo ? hi - lo : 0;
+        }
+        qleaf[(int64_t)i * g.P + k] = (double)ones;
+    }
+}
+
+hipError_t launch_ingest(int prec, const double *s, int64_t ld, double mu, double c, const Geom &g, Mat m,
+                         hipStream_t st) {
+    const unsigned nt = (unsigned)g.nb * g.nb;
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_ingest<double>, dim3(nt), dim3(256), 0, st, s, ld, mu, c, g, (double *)m.tiles, m.q);
+    else
+        hipLaunchKernelGGL(k_ingest<float>, dim3(nt), dim3(256), 0, st, s, ld, mu, c, g, (float *)m.tiles, m.q);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity(int prec, const Geom &g, Mat m, hipStream_t st) {
+    const unsigned nt = (unsigned)g.nb * g.nb;
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_identity<double>, dim3(nt), dim3(256), 0, st, g, (double *)m.tiles, m.q);
+    else
+        hipLaunchKernelGGL(k_identity<float>, dim3(nt), dim3(256), 0, st, g, (float *)m.tiles, m.q);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Norm pyramid: each block reduces an R x R region (R = min(S, 32)) of the
+// level of side S through up to five parent levels, each parent's squared
+// norm being (q00 + q01) + (q10 + q11).  With nrm != nullptr the launch is on
+// the leaf level and also writes the leaf norms of the real blocks.
+// blockIdx.y selects one of two operands.
+// ---------------------------------------------------------------------------
+struct PyrArgs {
+    double *q;
+    double *nrm;
+};
+
+__global__ __launch_bounds__(256) void k_pyramid(PyrArgs a0, PyrArgs a1, int P, int S, int nb, int leaf) {
+    __shared__ double buf[32 * 32];
+    const PyrArgs a = blockIdx.y == 0 ? a0 : a1;
+    const int R = S < 32 ? S : 32;
+    const int G = S / R;  // regions per side
+    const int gy = blockIdx.x / G, gx = blockIdx.x % G;
+    const double *lvl = a.q + dev_level_off(P, S);
+    for (int e = threadIdx.x; e < R * R; e += 256) {
+        const int r = e / R, c = e % R;
+        const int64_t gr = (int64_t)gy * R + r, gc = (int64_t)gx * R + c;
+        const double v = lvl[gr * S + gc];
+        buf[e] = v;
+        if (leaf && gr < nb && gc < nb) a.nrm[gr * nb + gc] = sqrt(v);
+    }
+    __syncthreads();
+    int s = R;
+    int Scur = S;
+    while (s > 1) {
+        const int h = s / 2;
+        double v = 0.0;
+        const int e = threadIdx.x;
+        if (e < h * h) {
+            const int pr = e / h, pc = e % h;
+            const double q00 = buf[(2 * pr) * s + 2 * pc], q01 = buf[(2 * pr) * s + 2 * pc + 1];
+            const double q10 = buf[(2 * pr + 1) * s + 2 * pc], q11 = buf[(2 * pr + 1) * s + 2 * pc + 1];
+            v = (q00 + q01) + (q10 + q11);
+        }
+        __syncthreads();
+        const int Spar = Scur / 2;
+        if (e < h * h) {
+            buf[e] = v;
+            const int pr = e / h, pc = e % h;
+            const int64_t gr = (int64_t)gy * h + pr, gc = (int64_t)gx * h + pc;
+            a.q[dev_level_off(P, Spar) + gr * Spar + gc] = v;
+        }
+        __syncthreads();
+        s = h;
+        Scur = Spar;
+    }
+}
+
+static hipError_t pyramid_impl(const Geom &g, Mat m0, Mat m1, int nprob, hipStream_t st) {
+    PyrArgs a0{m0.q, m0.nrm}, a1{m1.q, m1.nrm};
+    int S = g.P;
+    int leaf = 1;
+    while (true) {
+        const int R = S < 32 ? S : 32;
+        const int G = S / R;
+        hipLaunchKernelGGL(k_pyramid, dim3(G * G, nprob), dim3(256), 0, st, a0, a1, g.P, S, g.nb, leaf);
+        leaf = 0;
+        if (G == 1) break;
+        S = G;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramid(const Geom &g, Mat m, hipStream_t st) { return pyramid_impl(g, m, m, 1, st); }
+hipError_t launch_pyramid2(const Geom &g, Mat m0, Mat m1, hipStream_t st) {
+    return pyramid_impl(g, m0, m1, 2, st);
+}
+
+// ---------------------------------------------------------------------------
+// Cull: for output tile (i,j) keep every k with ||A_ik|| ||B_kj|| >= thr,
+// thr = tau * (||A|| * ||B||), in increasing k.  Flat enumeration: since a
+// parent's squared norm is a sum of non-negative children, every ancestor
+// triple of a kept leaf triple is kept, so this equals the recursive set.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_cull(CullProb p0, CullProb p1, int nb) {
+    const CullProb p = blockIdx.z == 0 ? p0 : p1;
+    const int i = blockIdx.y;
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= nb) return;
+    const double thr = p.tau * (sqrt(*p.rootA) * sqrt(*p.rootB));
+    const double *na = p.nrmA + (int64_t)i * nb;
+    const double *nbj = p.nrmB + j;
+    int32_t *out = p.kidx + ((int64_t)i * nb + j) * nb;
+    int c = 0;
+    for (int k = 0; k < nb; ++k) {
+        const double prod = na[k] * nbj[(int64_t)k * nb];
+        if (!(prod < thr)) out[c++] = k;
+    }
+    p.cnt[(int64_t)i * nb + j] = c;
+}
+
+hipError_t launch_cull(const Geom &g, const CullProb *probs, int nprob, hipStream_t st) {
+    const CullProb p1 = nprob > 1 ? probs[1] : probs[0];
+    hipLaunchKernelGGL(k_cull, dim3((g.nb + 63) / 64, g.nb, nprob), dim3(64), 0, st, probs[0], p1, g.nb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Leaf products on MFMA.  One workgroup per output tile (i,j); 64x64 tiles
+// use four waves, each owning a 32x32 quadrant (2x2 blocks of 16x16); 32x32
+// and 16x16 tiles use one wave.  For every retained k in increasing order the
+// A_ik and B_kj tiles are staged through LDS (rows padded by 16 bytes), the
+// next pair being fetched into registers while the current one is consumed.
+// Epilogue: the C tile and its squared norm (of the stored values, FP64);
+// in MODE_NSX the tile written is h = 1.5 I_n - 0.5 x and the FP64 partial
+// sums of (I_n - x)^2 and of the trace over the logical block.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef v4d acc_t;
+    typedef d2 vec_t;  // 16-byte chunk
+    static constexpr int VEC = 2;
+    __device__ static inline acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // accumulator element r of lane l holds row l/16 + 4r, column l%16
+    __device__ static inline int row_of(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+    typedef v4f acc_t;
+    typedef v4f vec_t;
+    static constexpr int VEC = 4;
+    __device__ static inline acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // accumulator element r of lane l holds row 4(l/16) + r, column l%16
+    __device__ static inline int row_of(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, int B>
+struct TileCfg {
+    static constexpr int WAVES = (B == 64) ? 4 : 1;
+    static constexpr int NT = 64 * WAVES;
+    static constexpr int Q = (B >= 32) ? 32 : 16;  // rows/cols of C per wave
+    static constexpr int NBLK = Q / 16;            // 16x16 MFMA blocks per wave side
+    static constexpr int VEC = Mfma<T>::VEC;
+    static constexpr int LD = B + VEC;             // padded LDS row (elements)
+    static constexpr int CHUNKS = B * B / VEC / NT;
+};
+
+template <typename T, int B, int MODE>
+__global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0, GemmProb p1, Geom g) {
+    using C = TileCfg<T, B>;
+    using M = Mfma<T>;
+    typedef typename M::acc_t acc_t;
+    typedef typename M::vec_t vec_t;
+    __shared__ __attribute__((aligned(16))) T As[B * C::LD];
+    __shared__ __attribute__((aligned(16))) T Bs[B * C::LD];
+    __shared__ double red[3 * C::WAVES];
+
+    const GemmProb p = blockIdx.y == 0 ? p0 : p1;
+    const int t = blockIdx.x;
+    const int nb = g.nb;
+    const int i = t / nb, j = t % nb;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (C::WAVES == 4) ? (w >> 1) : 0, wc = (C::WAVES == 4) ? (w & 1) : 0;
+    const int cnt = p.cnt[t];
+    const int32_t *list = p.kidx + (int64_t)t * nb;
+    const T *Ab = (const T *)p.A;
+    const T *Bb = (const T *)p.B;
+    constexpr int64_t TS = (int64_t)B * B;
+
+    acc_t acc[C::NBLK][C::NBLK];
+#pragma unroll
+    for (int bi = 0; bi < C::NBLK; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < C::NBLK; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0;
+
+    vec_t ra[C::CHUNKS], rb[C::CHUNKS];
+    if (cnt > 0) {
+        const int k = list[0];
+        const vec_t *a = (const vec_t *)(Ab + ((int64_t)i * nb + k) * TS);
+        const vec_t *b = (const vec_t *)(Bb + ((int64_t)k * nb + j) * TS);
+#pragma unroll
+        for (int c = 0; c < C::CHUNKS; ++c) {
+            ra[c] = a[tid + c * C::NT];
+            rb[c] = b[tid + c * C::NT];
+        }
+    }
+    for (int e = 0; e < cnt; ++e) {
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C::CHUNKS; ++c) {
+            const int el = (tid + c * C::NT) * C::VEC;
+            const int r = el / B, col = el % B;
+            *(vec_t *)&As[r * C::LD + col] = ra[c];
+            *(vec_t *)&Bs[r * C::LD + col] = rb[c];
+        }
+        __syncthreads();
+        if (e + 1 < cnt) {
+            const int k = list[e + 1];
+            const vec_t *a = (const vec_t *)(Ab + ((int64_t)i * nb + k) * TS);
+            const vec_t *b = (const vec_t *)(Bb + ((int64_t)k * nb + j) * TS);
+#pragma unroll
+            for (int c = 0; c < C::CHUNKS; ++c) {
+                ra[c] = a[tid + c * C::NT];
+                rb[c] = b[tid + c * C::NT];
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < B; kk += 4) {
+            T av[C::NBLK], bv[C::NBLK];
+#pragma unroll
+            for (int bi = 0; bi < C::NBLK; ++bi)
+                av[bi] = As[(wr * C::Q + bi * 16 + (lane & 15)) * C::LD + kk + (lane >> 4)];
+#pragma unroll
+            for (int bj = 0; bj < C::NBLK; ++bj)
+                bv[bj] = Bs[(kk + (lane >> 4)) * C::LD + wc * C::Q + bj * 16 + (lane & 15)];
+#pragma unroll
+            for (int bi = 0; bi < C::NBLK; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < C::NBLK; ++bj) acc[bi][bj] = M::mma(av[bi], bv[bj], acc[bi][bj]);
+        }
+    }
+
+    // epilogue
+    T *Ct = (T *)p.C + (int64_t)t * TS;
+    double qs = 0.0, r2 = 0.0, tr = 0.0;
+#pragma unroll
+    for (int bi = 0; bi < C::NBLK; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < C::NBLK; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wr * C::Q + bi * 16 + M::row_of(lane, r);
+                const int col = wc * C::Q + bj * 16 + (lane & 15);
+                const double x = (double)acc[bi][bj][r];
+                T out;
+                if (MODE == MODE_NSX) {
+                    const int64_t gi = (int64_t)i * B + row, gj = (int64_t)j * B + col;
+                    const bool diag = (gi == gj) && (gi < g.n);
+                    const bool logical = (gi < g.n) && (gj < g.n);
+                    const double h = (diag ? 1.5 : 0.0) - 0.5 * x;
+                    const double ex = (diag ? 1.0 : 0.0) - x;
+                    if (logical) r2 += ex * ex;
+                    if (diag) tr += x;
+                    out = (T)h;
+                } else {
+                    out = (T)x;
+                }
+                Ct[row * B + col] = out;
+                const double dv = (double)out;
+                qs += dv * dv;
+            }
+    qs = wave_sum(qs);
+    if (MODE == MODE_NSX) {
+        r2 = wave_sum(r2);
+        tr = wave_sum(tr);
+    }
+    if (lane == 0) {
+        red[w] = qs;
+        red[C::WAVES + w] = r2;
+        red[2 * C::WAVES + w] = tr;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int x = 0; x < C::WAVES; ++x) {
+            a += red[x];
+            b += red[C::WAVES + x];
+            c += red[2 * C::WAVES + x];
+        }
+        p.qC[(int64_t)i * g.P + j] = a;
+        if (MODE == MODE_NSX) {
+            p.part[2 * (int64_t)t] = b;
+            p.part[2 * (int64_t)t + 1] = c;
+        }
+    }
+}
+
+template <typename T, int B>
+static void gemm_dispatch_mode(int mode, const Geom &g, const GemmProb &a, const GemmProb &b, int nprob,
+                               hipStream_t st) {
+    dim3 grid((unsigned)g.nb * g.nb, nprob);
+    dim3 block(TileCfg<T, B>::NT);
+    if (mode == MODE_NSX)
+        hipLaunchKernelGGL((k_leaf_gemm<T, B, MODE_NSX>), grid, block, 0, st, a, b, g);
+    else
+        hipLaunchKernelGGL((k_leaf_gemm<T, B, MODE_PLAIN>), grid, block, 0, st, a, b, g);
+}
+
+template <typename T>
+static void gemm_dispatch_b(int mode, const Geom &g, const GemmProb &a, const GemmProb &b, int nprob,
+                            hipStream_t st) {
+    if (g.b == 64)
+        gemm_dispatch_mode<T, 64>(mode, g, a, b, nprob, st);
+    else if (g.b == 32)
+        gemm_dispatch_mode<T, 32>(mode, g, a, b, nprob, st);
+    else
+        gemm_dispatch_mode<T, 16>(mode, g, a, b, nprob, st);
+}
+
+hipError_t launch_gemm(int prec, int mode, const Geom &g, const GemmProb *probs, int nprob, hipStream_t st) {
+    const GemmProb p1 = nprob > 1 ? probs[1] : probs[0];
+    if (prec == P_F64)
+        gemm_dispatch_b<double>(mode, g, probs[0], p1, nprob, st);
+    else
+        gemm_dispatch_b<float>(mode, g, probs[0], p1, nprob, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Newton-Schulz reduction: r_k = sqrt(sum of per-tile (I-x)^2), t_k =
+// (n - trace)/n, and |R| of x_k (and of the update that produced y_k, z_k),
+// all summed in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_ns_reduce(const double *__restrict__ part, int64_t ntiles,
+                                                     const int32_t *__restrict__ cntX,
+                                                     const int32_t *__restrict__ cntY,
+                                                     const int32_t *__restrict__ cntZ, int64_t n, int k,
+                                                     double *hist_r, double *hist_t, int64_t *hist_nR,
+                                                     double *out2) {
+    __shared__ double sh[16];
+    double r2 = 0.0, tr = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
+    for (int64_t e = threadIdx.x; e < ntiles; e += 1024) {
+        r2 += part[2 * e];
+        tr += part[2 * e + 1];
+        cx += (double)cntX[e];
+        if (k > 0) {
+            cy += (double)cntY[e];
+            cz += (double)cntZ[e];
+        }
+    }
+    r2 = block_sum<1024>(r2, sh);
+    tr = block_sum<1024>(tr, sh);
+    cx = block_sum<1024>(cx, sh);
+    cy = block_sum<1024>(cy, sh);
+    cz = block_sum<1024>(cz, sh);
+    if (threadIdx.x == 0) {
+        const double r = sqrt(r2);
+        const double tk = ((double)n - tr) / (double)n;
+        hist_r[k] = r;
+        hist_t[k] = tk;
+        hist_nR[3 * k] = (int64_t)cx;
+        if (k > 0) {
+            hist_nR[3 * (k - 1) + 1] = (int64_t)cy;
+            hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
+        }
+        out2[0] = r;
+        out2[1] = tk;
+    }
+}
+
+hipError_t launch_ns_reduce(const Geom &g, const double *part, const int32_t *cntX, const int32_t *cntY,
+                            const int32_t *cntZ, int k, double *hist_r, double *hist_t, int64_t *hist_nR,
+                            double *out2, hipStream_t st) {
+    hipLaunchKernelGGL(k_ns_reduce, dim3(1), dim3(1024), 0, st, part, (int64_t)g.nb * g.nb, cntX, cntY, cntZ,
+                       g.n, k, hist_r, hist_t, hist_nR, out2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Egress: tile-major T -> row-major FP64, times or divided by `scale`.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_egress(const T *__restrict__ tiles, Geom g, double *__restrict__ out,
+                                                 int64_t ld, double scale, int divide) {
+    const int t = blockIdx.x;
+    const int i = t / g.nb, k = t % g.nb;
+    const int b = g.b;
+    const T *src = tiles + (int64_t)t * b * b;
+    for (int e = threadIdx.x; e < b * b; e += 256) {
+        const int r = e / b, c = e % b;
+        const int64_t gi = (int64_t)i * b + r, gj = (int64_t)k * b + c;
+        if (gi < g.n && gj < g.n) {
+            const double v = (double)src[e];
+            out[gi * ld + gj] = divide ? v / scale : v * scale;
+        }
+    }
+}
+
+hipError_t launch_egress(int prec, const Geom &g, const void *tiles, double *out, int64_t ld, double scale,
+                         int divide, hipStream_t st) {
+    const unsigned nt = (unsigned)g.nb * g.nb;
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_egress<double>, dim3(nt), dim3(256), 0, st, (const double *)tiles, g, out, ld, scale,
+                           divide);
+    else
+        hipLaunchKernelGGL(k_egress<float>, dim3(nt), dim3(256), 0, st, (const float *)tiles, g, out, ld, scale,
+                           divide);
+    return hipGetLastError();
+}
+
+// sqrt of every pyramid entry (squared norms -> norms).
+__global__ __launch_bounds__(256) void k_sqrt(const double *__restrict__ q, double *__restrict__ out, int64_t m) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < m) out[e] = sqrt(q[e]);
+}
+
+hipError_t launch_norms_out(const Geom &g, const double *q, double *out, hipStream_t st) {
+    const int64_t m = pyr_len(g.P);
+    hipLaunchKernelGGL(k_sqrt, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, q, out, m);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Retained-triple export: exclusive scan of per-tile counts in (i,j) order
+// (single block), then every tile scatters its (i,j,k) records.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict__ cnt, int64_t m,
+                                                       int64_t *__restrict__ offs, int64_t *__restrict__ total) {
+    __shared__ int64_t part[1024];
+    const int64_t per = (m + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per, hi = lo + per < m ? lo + per : m;
+    int64_t s = 0;
+    for (int64_t e = lo; e < hi; ++e) s += cnt[e];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int x = 0; x < 1024; ++x) {
+            const int64_t v = part[x];
+            part[x] = run;
+            run += v;
+        }
+        *total = run;
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int64_t e = lo; e < hi; ++e) {
+        offs[e] = run;
+        run += cnt[e];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_write_triples(const int32_t *__restrict__ cnt,
+                                                       const int32_t *__restrict__ kidx,
+                                                       const int64_t *__restrict__ offs, int nb,
+                                                       int32_t *__restrict__ trip) {
+    const int64_t t = blockIdx.x;
+    const int i = (int)(t / nb), j = (int)(t % nb);
+    const int c = cnt[t];
+    const int64_t o = offs[t];
+    for (int e = threadIdx.x; e < c; e += 64) {
+        trip[3 * (o + e) + 0] = i;
+        trip[3 * (o + e) + 1] = j;
+        trip[3 * (o + e) + 2] = kidx[t * nb + e];
+    }
+}
+
+hipError_t launch_count_triples(const Geom &g, const int32_t *cnt, int64_t *offs, int64_t *total,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, (int64_t)g.nb * g.nb, offs, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_triples(const Geom &g, const int32_t *cnt, const int32_t *kidx, const int64_t *offs,
+                                int32_t *triples, hipStream_t st) {
+    hipLaunchKernelGGL(k_write_triples, dim3((unsigned)g.nb * g.nb), dim3(64), 0, st, cnt, kidx, offs, g.nb,
+                       triples);
+    return hipGetLastError();
+}
+
+}  // namespace spk

@@ -1,0 +1,345 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Norm pyramids to 1e-14 relative; retained triples bit-exact (near-ties within
+1e-12 of the threshold excluded); FP64 products to 1e-13 of ||A|| ||B||; FP64
+Newton-Schulz iterates to 1e-12 relative (Frobenius), with identical
+iteration counts and retained-triple histories.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_05856_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1508_05856_amd import spamm
+    c = spamm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def decaying(n, seed=0, rate=0.15):
+    g = np.random.default_rng(seed)
+    i = np.arange(n)
+    return np.exp(-rate * np.abs(i[:, None] - i[None, :])) * g.standard_normal((n, n))
+
+
+def near_tie_mask(a, b, leaf, tau):
+    """Leaf triples whose norm product is within 1e-12 (relative) of the threshold."""
+    la = oracle.norms(a, leaf)
+    lb = oracle.norms(b, leaf)
+    nb = -(-a.shape[0] // leaf)
+    na, nbm = la[0][:nb, :nb], lb[0][:nb, :nb]
+    thr = tau * (la[-1][0, 0] * lb[-1][0, 0])
+    prod = na[:, None, :] * nbm.T[None, :, :]   # [i, j, k] = ||A_ik|| ||B_kj||
+    return np.abs(prod - thr) <= 1e-12 * thr if thr > 0 else np.zeros_like(prod, dtype=bool)
+
+
+def rel(x, ref):
+    return np.linalg.norm(x - ref) / np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------------------
+# norms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,leaf", [(512, 32), (300, 32), (4096, 64), (1000, 64), (77, 16), (16, 16)])
+def test_norm_pyramid(ctx, n, leaf):
+    a = decaying(n, seed=n)
+    pyr, root = ctx.spamm_norms(dev(a), leaf)
+    levels = oracle.norms(a, leaf)
+    ref = np.concatenate([lv.ravel() for lv in levels])
+    got = host(pyr)
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=0)
+    assert root == pytest.approx(levels[-1][0, 0], rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# products
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,leaf", [(512, 32), (200, 32), (256, 64), (333, 64), (96, 16), (50, 16)])
+def test_multiply_tau_zero_is_gemm(ctx, n, leaf):
+    a = decaying(n, seed=1)
+    b = decaying(n, seed=2)
+    C, stats, _ = ctx.spamm_multiply(dev(a), dev(b), 0.0, leaf)
+    nb = -(-n // leaf)
+    assert stats["retained"] == nb ** 3
+    ref = a @ b
+    assert np.abs(host(C) - ref).max() <= 1e-13 * np.linalg.norm(a) * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("tau", [1e-8, 1e-6, 1e-4, 1e-3, 1e-2])
+@pytest.mark.parametrize("n,leaf", [(512, 32), (450, 32), (640, 64), (200, 16)])
+def test_multiply_matches_oracle(ctx, tau, n, leaf):
+    a = decaying(n, seed=3, rate=0.05)
+    b = decaying(n, seed=4, rate=0.08)
+    C, stats, trip = ctx.spamm_multiply(dev(a), dev(b), tau, leaf, triples=True)
+    Co, Ro, cnt = oracle.spamm(a, b, leaf, tau)
+    ties = near_tie_mask(a, b, leaf, tau)
+    got = set(map(tuple, host(trip).tolist()))
+    ref = set(map(tuple, Ro.tolist()))
+    diff = got ^ ref
+    assert all(ties[i, j, k] for (i, j, k) in diff), f"{len(diff)} non-tie differences"
+    if not ties.any():
+        assert stats["retained"] == cnt
+        np.testing.assert_array_equal(host(trip), Ro)   # sorted (i, j, k)
+        assert np.abs(host(C) - Co).max() <= 1e-13 * np.linalg.norm(a) * np.linalg.norm(b)
+    assert stats["thr"] == pytest.approx(tau * np.linalg.norm(a) * np.linalg.norm(b), rel=1e-13)
+
+
+def test_multiply_block_diagonal_and_limits(ctx):
+    b, nb = 32, 8
+    n = b * nb
+    g = np.random.default_rng(5)
+    a = np.zeros((n, n))
+    for i in range(nb):
+        a[i * b:(i + 1) * b, i * b:(i + 1) * b] = g.standard_normal((b, b))
+    _, st, trip = ctx.spamm_multiply(dev(a), dev(a), 1e-3, b, triples=True)
+    np.testing.assert_array_equal(host(trip), np.array([(i, i, i) for i in range(nb)]))
+    C, st, _ = ctx.spamm_multiply(dev(a), dev(a), 1.5, b, triples=True)
+    assert st["retained"] == 0 and np.count_nonzero(host(C)) == 0
+
+
+def test_multiply_capacity_error(ctx):
+    from paper_1508_05856_amd import spamm
+    a = decaying(128, seed=6)
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.spamm_multiply(dev(a), dev(a), 0.0, 32, triples=True, cap=10)
+    assert e.value.status == spamm.ECAPACITY
+
+
+def test_multiply_f32_error_vs_oracle(ctx):
+    n, leaf, tau = 512, 32, 1e-6
+    a = decaying(n, seed=7, rate=0.05)
+    b = decaying(n, seed=8, rate=0.05)
+    C, st, _ = ctx.spamm_multiply(dev(a), dev(b), tau, leaf, prec="f32")
+    Co, _, cnt = oracle.spamm(a.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64),
+                              leaf, tau, want_triples=False)
+    assert st["retained"] == cnt
+    err = np.abs(host(C) - Co).max() / (np.linalg.norm(a) * np.linalg.norm(b))
+    assert err < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Newton-Schulz
+# ---------------------------------------------------------------------------
+
+def check_ns(ctx, s, leaf, tau, tol, maxit, **kw):
+    Y, Z, info = ctx.ns_sqrt(dev(s), tau, tol, maxit, leaf=leaf, **kw)
+    ores = oracle.ns_sqrt(s, leaf, tau, tol, maxit, tau_s=kw.get("tau_s", -1.0), mu_rel=kw.get("mu_rel", 0.0),
+                          stagnation_stop=kw.get("stagnation_stop", False))
+    r, t, nR = ctx.ns_history()
+    assert info["status"] == ores["status"]
+    assert info["iterations"] == ores["iterations"]
+    assert info["scale"] == ores["scale"]
+    np.testing.assert_array_equal(nR, ores["nR"])
+    # r near the rounding floor (~1e-12) differs in absolute terms only
+    np.testing.assert_allclose(r, ores["r"], rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(t, ores["t"], rtol=1e-8, atol=1e-14)
+    assert rel(host(Y), ores["Y"]) <= 1e-12
+    assert rel(host(Z), ores["Z"]) <= 1e-12
+    return host(Y), host(Z), info, ores
+
+
+def test_ns_c1_plain_fp64(ctx):
+    cfg = inputs.config_c1()
+    Y, Z, info, ores = check_ns(ctx, cfg["s"], cfg["leaf"], cfg["tau"], cfg["tol"], cfg["maxit"])
+    assert info["status"] == 1 and info["iterations"] == 40   # stalls above 1e-10 (tau plateau)
+    n = cfg["s"].shape[0]
+    assert np.linalg.norm(Y @ Z - np.eye(n)) < 1e-4
+
+
+def test_ns_c1_stagnation_stop(ctx):
+    cfg = inputs.config_c1()
+    check_ns(ctx, cfg["s"], cfg["leaf"], cfg["tau"], cfg["tol"], cfg["maxit"], stagnation_stop=True)
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-8, 1e-6, 1e-4])
+def test_ns_kms_taus(ctx, tau):
+    s = inputs.kms(384, 0.8)
+    check_ns(ctx, s, 32, tau, 1e-10, 30, stagnation_stop=True)
+
+
+@pytest.mark.parametrize("n,leaf", [(300, 32), (200, 64), (130, 16), (1000, 64)])
+def test_ns_ragged_gaussian(ctx, n, leaf):
+    m = inputs.smallest_cube(n)
+    s = inputs.gramian_from_positions(inputs.gauss_positions(m, 1.1, 0.1, 3, n))
+    check_ns(ctx, s, leaf, 1e-6, 1e-9, 25, stagnation_stop=True)
+
+
+def test_ns_tau_zero_vs_eigh(ctx):
+    s = inputs.kms(256, 0.7)
+    Y, Z, info = ctx.ns_sqrt(dev(s), 0.0, 1e-12, 40, leaf=32)
+    assert info["status"] == 0
+    w, V = np.linalg.eigh(s)
+    assert rel(host(Y), (V * np.sqrt(w)) @ V.T) < 1e-12
+    assert rel(host(Z), (V / np.sqrt(w)) @ V.T) < 1e-12
+
+
+def test_ns_separate_tau_s(ctx):
+    s = inputs.kms(256, 0.85)
+    check_ns(ctx, s, 32, 1e-4, 1e-10, 20, tau_s=1e-6, stagnation_stop=True)
+
+
+def test_ns_regularised(ctx):
+    s = inputs.gauss_gramian(7, 0.6)
+    check_ns(ctx, s, 32, 1e-6, 1e-8, 30, mu_rel=1e-4, stagnation_stop=True)
+
+
+def test_ns_leading_dimension(ctx):
+    n, ld = 200, 256
+    s = inputs.kms(n, 0.6)
+    big = torch.zeros((n, ld), dtype=torch.float64, device="cuda")
+    big[:, :n] = dev(s)
+    # a row-major n x n view with leading dimension ld
+    sv = torch.as_strided(big, (n, n), (ld, 1))
+    Ybig = torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda")
+    Zbig = torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda")
+    Y, Z, info = ctx.ns_sqrt(sv, 1e-8, 1e-10, 20, leaf=32, Y=torch.as_strided(Ybig, (n, n), (ld, 1)),
+                             Z=torch.as_strided(Zbig, (n, n), (ld, 1)))
+    ores = oracle.ns_sqrt(s, 32, 1e-8, 1e-10, 20)
+    assert rel(host(Ybig)[:, :n], ores["Y"]) < 1e-12
+    assert np.all(host(Ybig)[:, n:] == 7.0)     # padding columns untouched
+
+
+def test_ns_errors(ctx):
+    from paper_1508_05856_amd import spamm
+    s = inputs.kms(96, 0.6)
+    bad = s.copy()
+    bad[3, 5] = np.nan
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.ns_sqrt(dev(bad), 1e-6, 1e-10, 10)
+    assert e.value.status == spamm.EINVAL
+    asym = s.copy()
+    asym[3, 5] += 1e-9
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.ns_sqrt(dev(asym), 1e-6, 1e-10, 10)
+    assert e.value.status == spamm.EINVAL
+    indef = s.copy()
+    indef[0, 0] = -1.0
+    _, _, info = ctx.ns_sqrt(dev(indef), 0.0, 1e-10, 40, raise_on_error=False)
+    assert info["status"] == spamm.EDIVERGED
+    assert oracle.ns_sqrt(indef, 32, 0.0, 1e-10, 40)["status"] == oracle.EDIVERGED
+    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-6, 1e-10, 0)
+    c = np.abs(s).sum(axis=1).max()
+    assert info["status"] == spamm.NOT_CONVERGED and info["iterations"] == 0
+    np.testing.assert_allclose(host(Y), s / c * np.sqrt(c), rtol=1e-15)
+    for kw in (dict(tau=-1.0), dict(tol=0.0), dict(maxit=-1), dict(leaf=48)):
+        args = dict(tau=1e-6, tol=1e-10, maxit=10, leaf=32)
+        args.update(kw)
+        with pytest.raises(spamm.SpammError) as e:
+            ctx.ns_sqrt(dev(s), args["tau"], args["tol"], args["maxit"], leaf=args["leaf"])
+        assert e.value.status == spamm.EINVAL
+
+
+def test_ns_deterministic(ctx):
+    cfg = inputs.config_c1()
+    s = dev(cfg["s"])
+    Y1, Z1, _ = ctx.ns_sqrt(s, cfg["tau"], cfg["tol"], 12, leaf=32)
+    Y1, Z1 = host(Y1), host(Z1)
+    Y2, Z2, _ = ctx.ns_sqrt(s, cfg["tau"], cfg["tol"], 12, leaf=32)
+    np.testing.assert_array_equal(Y1, host(Y2))
+    np.testing.assert_array_equal(Z1, host(Z2))
+
+
+# ---------------------------------------------------------------------------
+# full-size Gaussian workload (n = 4096, leaf 64), as the benchmark runs it
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c2():
+    return inputs.config_c2(1e-6)
+
+
+def test_c2_first_updates_match_oracle(ctx, c2):
+    """Two X products and one (Y, Z) update at full size, compared in full."""
+    s = c2["s"]
+    ores = oracle.ns_sqrt(s, 64, c2["tau"], c2["tol"], 1)
+    Y, Z, info = ctx.ns_sqrt(dev(s), c2["tau"], c2["tol"], 1, leaf=64)
+    r, t, nR = ctx.ns_history()
+    assert info["iterations"] == ores["iterations"] == 1
+    np.testing.assert_array_equal(nR, ores["nR"])
+    # the oracle sums 16.7M squares serially: its relative rounding error can reach
+    # ~1e-11 (the worst-case bound is n^2 u ~ 2e-9); the GPU sums in a tree
+    np.testing.assert_allclose(r, ores["r"], rtol=1e-10)
+    assert rel(host(Y), ores["Y"]) <= 1e-12
+    assert rel(host(Z), ores["Z"]) <= 1e-12
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden_cases():
+    return sorted(f[:-5] for f in os.listdir(GOLDEN) if f.startswith("gauss_m16") and f.endswith(".json"))
+
+
+@pytest.mark.parametrize("name", golden_cases())
+def test_c2_full_solve_matches_oracle_history(ctx, c2, name):
+    """A complete full-size solve against the oracle's stored history (written by
+    tests/golden/make_golden.py): same status and iteration count, the same
+    retained-triple count for every product, r_k to 1e-9 relative."""
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        gold = json.load(f)
+    _, _, info = ctx.ns_sqrt(dev(c2["s"]), gold["tau"], gold["tol"], gold["maxit"], leaf=gold["leaf"],
+                             tau_s=gold["tau_s"], stagnation_stop=gold["stagnation_stop"], raise_on_error=False)
+    r, t, nR = ctx.ns_history()
+    assert info["status"] == gold["status"]
+    assert info["iterations"] == gold["iterations"]
+    assert info["scale"] == gold["scale"]
+    np.testing.assert_array_equal(nR, np.array(gold["nR"]))
+    np.testing.assert_allclose(r, gold["r"], rtol=1e-9)
+    np.testing.assert_allclose(t, gold["t"], rtol=1e-6, atol=1e-12)
+
+
+def test_c2_sampled_product_and_invariants(ctx, c2):
+    """Full-size solve as the benchmark runs it; then x = y (x)_tau z of the result
+    through the library, checked tile by tile against the oracle on sampled tiles."""
+    s = c2["s"]
+    n = s.shape[0]
+    tau = 1e-8
+    Yd, Zd, info = ctx.ns_sqrt(dev(s), tau, 1e-10, 40, leaf=64, stagnation_stop=True)
+    assert info["status"] in (0, 2)
+    Y, Z = host(Yd), host(Zd)
+    c = info["scale"]
+    assert np.linalg.norm(Y @ Z - np.eye(n)) < 2 * info["resid"] + 1e-6
+    ys, zs = Y / np.sqrt(c), Z * np.sqrt(c)
+    Cd, st, _ = ctx.spamm_multiply(dev(ys), dev(zs), tau, 64)
+    tiles = [(0, 0), (5, 9), (17, 17), (40, 3), (63, 63), (31, 32)]
+    out, counts = oracle.spamm_tiles(ys, zs, 64, tau, tiles)
+    C = host(Cd)
+    for (i, j), o in zip(tiles, out):
+        got = C[i * 64:(i + 1) * 64, j * 64:(j + 1) * 64]
+        assert np.abs(got - o).max() <= 1e-13 * np.linalg.norm(ys) * np.linalg.norm(zs)
+
+
+# ---------------------------------------------------------------------------
+# reduced-precision leaves: error against the FP64 oracle
+# ---------------------------------------------------------------------------
+
+def test_ns_f32_leaves_error_vs_fp64_oracle(ctx):
+    s = inputs.kms(512, 0.7)
+    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-8, 1e-5, 40, leaf=32, prec="f32", stagnation_stop=True)
+    ores = oracle.ns_sqrt(s, 32, 1e-8, 1e-5, 40, stagnation_stop=True)
+    ey, ez = rel(host(Y), ores["Y"]), rel(host(Z), ores["Z"])
+    print(f"f32 leaves: relY={ey:.2e} relZ={ez:.2e} iterations {info['iterations']} vs {ores['iterations']}")
+    assert ey <= 5e-6 and ez <= 5e-6
