@@ -40,7 +40,7 @@ def parse():
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--maxit", type=int, default=40)
     p.add_argument("--literal-stop", action="store_true", help="disable the stagnation stop")
-    p.add_argument("--cpu-sample-iters", type=int, default=2)
+    p.add_argument("--cpu-sample-iters", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--dump-launches", default=None, help="write per-launch (flops, ms) of the timed steps")
     return p.parse_args()

@@ -57,6 +57,8 @@ enum Slot {
     S_SCAL,                            // device scalars
     S_HIST_R, S_HIST_T, S_HIST_NR,     // per-iteration records
     S_OFFS,                            // triple export offsets
+    S_ORDER,                           // Morton order of output tiles
+    S_WORK,                            // longest-first work list of one launch
     S_COUNT
 };
 
@@ -72,6 +74,7 @@ struct spamm_ctx {
     void *buf[S_COUNT] = {};
     size_t cap[S_COUNT] = {};
     double *pinned = nullptr;  // 64 doubles of pinned host memory
+    int order_nb = -1;         // nb for which S_ORDER holds the tile order
     std::vector<double> hist_r, hist_t;
     std::vector<int64_t> hist_nR;
     // launch timing
@@ -130,6 +133,14 @@ int ensure_mats(spamm_ctx *ctx, const Geom &g, int prec, int nmat, int nlist) {
         TRY(ensure(ctx, S_KIDX0 + l, kidx));
     }
     TRY(ensure(ctx, S_SCAL, 64 * sizeof(double)));
+    if (ctx->order_nb != g.nb) {
+        TRY(ensure(ctx, S_ORDER, (size_t)g.nb * g.nb * sizeof(int32_t)));
+        std::vector<int32_t> order((size_t)g.nb * g.nb);
+        tile_order(g.nb, order.data());
+        HIPCHK(hipMemcpy(ctx->buf[S_ORDER], order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        ctx->order_nb = g.nb;
+    }
+    TRY(ensure(ctx, S_WORK, (size_t)2 * g.nb * g.nb * sizeof(int32_t)));
     return SPAMM_OK;
 }
 
@@ -157,6 +168,15 @@ void prof_end(spamm_ctx *ctx, hipStream_t st, int kind, hipEvent_t a) {
         HIPCHK(call);                                  \
         prof_end(ctx, st, kind, ev_);                  \
     } while (0)
+
+const int32_t *order_of(spamm_ctx *ctx) { return slot_ptr<int32_t>(ctx, S_ORDER); }
+
+// Longest-first work list for the products whose counts are in `probs`.
+hipError_t plan_gemm(spamm_ctx *ctx, const Geom &g, const GemmProb *probs, int nprob, hipStream_t st) {
+    return launch_lpt_order(g, probs[0].cnt, nprob > 1 ? probs[1].cnt : probs[0].cnt, nprob, order_of(ctx),
+                            slot_ptr<int32_t>(ctx, S_WORK), st);
+}
+const int32_t *work_of(spamm_ctx *ctx) { return slot_ptr<int32_t>(ctx, S_WORK); }
 
 Mat mat_of(spamm_ctx *ctx, int m) {
     Mat x;
@@ -300,7 +320,8 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     CullProb cp = cull_prob(g, a, b, tau, ctx, 0);
     TIMED(K_CULL, launch_cull(g, &cp, 1, st));
     GemmProb gp = gemm_prob(a, b, c, ctx, 0, nullptr);
-    TIMED(K_GEMM, launch_gemm(kp, MODE_PLAIN, g, &gp, 1, st));
+    HIPCHK(plan_gemm(ctx, g, &gp, 1, st));
+    TIMED(K_GEMM, launch_gemm(kp, MODE_PLAIN, g, work_of(ctx), &gp, 1, st));
     HIPCHK(launch_egress(kp, g, c.tiles, C, ld, 1.0, 0, st));
     int status = SPAMM_OK;
     if (stats || triples) {
@@ -411,7 +432,8 @@ int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, in
         CullProb cx = cull_prob(g, y, z, tau, ctx, 0);
         TIMED(K_CULL, launch_cull(g, &cx, 1, st));
         GemmProb gx = gemm_prob(y, z, h, ctx, 0, part);
-        TIMED(K_GEMM, launch_gemm(kp, MODE_NSX, g, &gx, 1, st));
+        HIPCHK(plan_gemm(ctx, g, &gx, 1, st));
+        TIMED(K_GEMM, launch_gemm(kp, MODE_NSX, g, work_of(ctx), &gx, 1, st));
         HIPCHK(launch_ns_reduce(g, part, cx.cnt, slot_ptr<int32_t>(ctx, S_CNT1), slot_ptr<int32_t>(ctx, S_CNT2), k,
                                 hist_r, hist_t, hist_nR, scal + 8, st));
         TIMED(K_PYR, launch_pyramid(g, h, st));
@@ -445,7 +467,8 @@ int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, in
         CullProb cu[2] = {cull_prob(g, h, y, tau_s, ctx, 1), cull_prob(g, z, h, tau, ctx, 2)};
         TIMED(K_CULL, launch_cull(g, cu, 2, st));
         GemmProb gu[2] = {gemm_prob(h, y, ynm, ctx, 1, nullptr), gemm_prob(z, h, znm, ctx, 2, nullptr)};
-        TIMED(K_GEMM, launch_gemm(kp, MODE_PLAIN, g, gu, 2, st));
+        HIPCHK(plan_gemm(ctx, g, gu, 2, st));
+        TIMED(K_GEMM, launch_gemm(kp, MODE_PLAIN, g, work_of(ctx), gu, 2, st));
         TIMED(K_PYR, launch_pyramid2(g, ynm, znm, st));
         yi = yn;
         zi = zn;

@@ -46,6 +46,10 @@ struct CullProb {
     int32_t *kidx;        // nb*nb*nb: R_ij at kidx[(i*nb+j)*nb ...], increasing k
 };
 
+// Dispatch order of output tiles for the leaf products: the tiles in Morton
+// (Z) order, so that a contiguous range of ranks is a compact 2-D block of C.
+void tile_order(int nb, int32_t *order /* nb*nb */);
+
 // Leaf products of one C = A (x)_tau B over the culled lists.
 struct GemmProb {
     const void *A;
@@ -67,7 +71,13 @@ hipError_t launch_identity(int prec, const Geom &g, Mat m, hipStream_t st);
 hipError_t launch_pyramid(const Geom &g, Mat m, hipStream_t st);
 hipError_t launch_pyramid2(const Geom &g, Mat m0, Mat m1, hipStream_t st);
 hipError_t launch_cull(const Geom &g, const CullProb *probs, int nprob, hipStream_t st);
-hipError_t launch_gemm(int prec, int mode, const Geom &g, const GemmProb *probs, int nprob, hipStream_t st);
+// Longest-first work list for one leaf-product launch: every (problem, tile)
+// pair, encoded p*nb*nb + t, ordered by decreasing |R_ij| (counting sort in
+// one workgroup).  `morton` gives the base order inside each count bucket.
+hipError_t launch_lpt_order(const Geom &g, const int32_t *cnt0, const int32_t *cnt1, int nprob,
+                            const int32_t *morton, int32_t *work, hipStream_t st);
+hipError_t launch_gemm(int prec, int mode, const Geom &g, const int32_t *work, const GemmProb *probs, int nprob,
+                       hipStream_t st);
 hipError_t launch_ns_reduce(const Geom &g, const double *part, const int32_t *cntX, const int32_t *cntY,
                             const int32_t *cntZ, int k, double *hist_r, double *hist_t, int64_t *hist_nR,
                             double *out2, hipStream_t st);

@@ -36,6 +36,20 @@ int64_t level_off(int P, int S) {
     return o;
 }
 
+void tile_order(int nb, int32_t *order) {
+    int P = 1;
+    while (P < nb) P <<= 1;
+    int m = 0;
+    for (int64_t z = 0; z < (int64_t)P * P; ++z) {
+        int i = 0, j = 0;
+        for (int bit = 0; (1 << bit) < P; ++bit) {
+            j |= (int)((z >> (2 * bit)) & 1) << bit;
+            i |= (int)((z >> (2 * bit + 1)) & 1) << bit;
+        }
+        if (i < nb && j < nb) order[m++] = i * nb + j;
+    }
+}
+
 __device__ inline int64_t dev_level_off(int P, int S) {
     int64_t o = 0;
     for (int64_t T = P; T > S; T >>= 1) o += T * T;
@@ -394,24 +408,39 @@ struct TileCfg {
     static constexpr int NT = 64 * WAVES;
     static constexpr int Q = (B >= 32) ? 32 : 16;  // rows/cols of C per wave
     static constexpr int NBLK = Q / 16;            // 16x16 MFMA blocks per wave side
-    static constexpr int VEC = Mfma<T>::VEC;
-    static constexpr int LD = B + VEC;             // padded LDS row (elements)
-    static constexpr int CHUNKS = B * B / VEC / NT;
+    static constexpr int VEC = Mfma<T>::VEC;       // elements per 16-byte chunk
+    static constexpr int KS = (B == 64) ? 32 : B;  // k extent of one pipeline stage
+    static constexpr int SPT = B / KS;             // stages per retained triple
+    // LDS row strides (elements).  A stage (B x KS) is read by fragments
+    // A[row + l%16][k + l/16]: a stride of KS + 16 bytes puts the 16 rows and
+    // the k offsets of a 32-lane (FP64) or 64-lane (FP32) access in distinct
+    // banks.  B stage (KS x B) is read as B[k + l/16][col + l%16]: a stride of
+    // B + 16 elements moves consecutive k rows by half (FP64) or a quarter
+    // (FP32) of the 64 banks.
+    static constexpr int LDA = KS + VEC;
+    static constexpr int LDB = (B == 16) ? 16 : B + 16;
+    static constexpr int A_CH = B * KS / VEC / NT;  // 16-byte chunks per thread per stage
+    static constexpr int B_CH = KS * B / VEC / NT;
 };
 
 template <typename T, int B, int MODE>
-__global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0, GemmProb p1, Geom g) {
+__global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0, GemmProb p1, Geom g,
+                                                                    const int32_t *__restrict__ order) {
     using C = TileCfg<T, B>;
     using M = Mfma<T>;
     typedef typename M::acc_t acc_t;
     typedef typename M::vec_t vec_t;
-    __shared__ __attribute__((aligned(16))) T As[B * C::LD];
-    __shared__ __attribute__((aligned(16))) T Bs[B * C::LD];
+    // two pipeline buffers for each operand
+    __shared__ __attribute__((aligned(16))) T As[2][B * C::LDA];
+    __shared__ __attribute__((aligned(16))) T Bs[2][C::KS * C::LDB];
     __shared__ double red[3 * C::WAVES];
 
-    const GemmProb p = blockIdx.y == 0 ? p0 : p1;
-    const int t = blockIdx.x;
     const int nb = g.nb;
+    const int w_item = order[blockIdx.x];
+    const int T_tiles = nb * nb;
+    const bool second = w_item >= T_tiles;
+    const GemmProb p = second ? p1 : p0;
+    const int t = second ? w_item - T_tiles : w_item;
     const int i = t / nb, j = t % nb;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (C::WAVES == 4) ? (w >> 1) : 0, wc = (C::WAVES == 4) ? (w & 1) : 0;
@@ -420,6 +449,7 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
     const T *Ab = (const T *)p.A;
     const T *Bb = (const T *)p.B;
     constexpr int64_t TS = (int64_t)B * B;
+    const int S = cnt * C::SPT;  // pipeline stages
 
     acc_t acc[C::NBLK][C::NBLK];
 #pragma unroll
@@ -429,51 +459,72 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0;
 
-    vec_t ra[C::CHUNKS], rb[C::CHUNKS];
-    if (cnt > 0) {
-        const int k = list[0];
-        const vec_t *a = (const vec_t *)(Ab + ((int64_t)i * nb + k) * TS);
-        const vec_t *b = (const vec_t *)(Bb + ((int64_t)k * nb + j) * TS);
+    // stage s covers k-columns [ks*KS, ks*KS+KS) of triple (i, j, list[s/SPT])
+    auto gload = [&](int s, vec_t *ra, vec_t *rb) {
+        const int k = list[s / C::SPT];
+        const int ks = s % C::SPT;
+        const T *a = Ab + ((int64_t)i * nb + k) * TS + ks * C::KS;
+        const vec_t *b = (const vec_t *)(Bb + ((int64_t)k * nb + j) * TS + (int64_t)ks * C::KS * B);
 #pragma unroll
-        for (int c = 0; c < C::CHUNKS; ++c) {
-            ra[c] = a[tid + c * C::NT];
-            rb[c] = b[tid + c * C::NT];
-        }
-    }
-    for (int e = 0; e < cnt; ++e) {
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < C::CHUNKS; ++c) {
+        for (int c = 0; c < C::A_CH; ++c) {
             const int el = (tid + c * C::NT) * C::VEC;
-            const int r = el / B, col = el % B;
-            *(vec_t *)&As[r * C::LD + col] = ra[c];
-            *(vec_t *)&Bs[r * C::LD + col] = rb[c];
-        }
-        __syncthreads();
-        if (e + 1 < cnt) {
-            const int k = list[e + 1];
-            const vec_t *a = (const vec_t *)(Ab + ((int64_t)i * nb + k) * TS);
-            const vec_t *b = (const vec_t *)(Bb + ((int64_t)k * nb + j) * TS);
-#pragma unroll
-            for (int c = 0; c < C::CHUNKS; ++c) {
-                ra[c] = a[tid + c * C::NT];
-                rb[c] = b[tid + c * C::NT];
-            }
+            ra[c] = *(const vec_t *)(a + (el / C::KS) * B + el % C::KS);
         }
 #pragma unroll
-        for (int kk = 0; kk < B; kk += 4) {
+        for (int c = 0; c < C::B_CH; ++c) rb[c] = b[tid + c * C::NT];
+    };
+    auto sstore = [&](int buf, const vec_t *ra, const vec_t *rb) {
+#pragma unroll
+        for (int c = 0; c < C::A_CH; ++c) {
+            const int el = (tid + c * C::NT) * C::VEC;
+            *(vec_t *)&As[buf][(el / C::KS) * C::LDA + el % C::KS] = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < C::B_CH; ++c) {
+            const int el = (tid + c * C::NT) * C::VEC;
+            *(vec_t *)&Bs[buf][(el / B) * C::LDB + el % B] = rb[c];
+        }
+    };
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int kk = 0; kk < C::KS; kk += 4) {
             T av[C::NBLK], bv[C::NBLK];
 #pragma unroll
             for (int bi = 0; bi < C::NBLK; ++bi)
-                av[bi] = As[(wr * C::Q + bi * 16 + (lane & 15)) * C::LD + kk + (lane >> 4)];
+                av[bi] = As[buf][(wr * C::Q + bi * 16 + (lane & 15)) * C::LDA + kk + (lane >> 4)];
 #pragma unroll
             for (int bj = 0; bj < C::NBLK; ++bj)
-                bv[bj] = Bs[(kk + (lane >> 4)) * C::LD + wc * C::Q + bj * 16 + (lane & 15)];
+                bv[bj] = Bs[buf][(kk + (lane >> 4)) * C::LDB + wc * C::Q + bj * 16 + (lane & 15)];
 #pragma unroll
             for (int bi = 0; bi < C::NBLK; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < C::NBLK; ++bj) acc[bi][bj] = M::mma(av[bi], bv[bj], acc[bi][bj]);
         }
+    };
+
+    // Software pipeline: LDS buffers alternate; register sets R0/R1 hold the
+    // stages two and one ahead of the one being multiplied, so every global
+    // load has two stages of MFMA work to arrive.  One barrier per stage.
+    vec_t ra0[C::A_CH], rb0[C::B_CH], ra1[C::A_CH], rb1[C::B_CH];
+    if (S > 0) {
+        gload(0, ra0, rb0);
+        if (S > 1) gload(1, ra1, rb1);
+        sstore(0, ra0, rb0);
+        if (S > 2) gload(2, ra0, rb0);
+    }
+    __syncthreads();
+    for (int s = 0; s < S; s += 2) {
+        // even stage s: LDS buffer 0; stage s+1 waits in R1, stage s+2 in R0
+        if (s + 1 < S) sstore(1, ra1, rb1);
+        if (s + 3 < S) gload(s + 3, ra1, rb1);
+        compute(0);
+        __syncthreads();
+        if (s + 1 >= S) break;
+        // odd stage s+1: LDS buffer 1; stage s+2 waits in R0, stage s+3 in R1
+        if (s + 2 < S) sstore(0, ra0, rb0);
+        if (s + 4 < S) gload(s + 4, ra0, rb0);
+        compute(1);
+        __syncthreads();
     }
 
     // epilogue
@@ -532,33 +583,79 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
 }
 
 template <typename T, int B>
-static void gemm_dispatch_mode(int mode, const Geom &g, const GemmProb &a, const GemmProb &b, int nprob,
-                               hipStream_t st) {
-    dim3 grid((unsigned)g.nb * g.nb, nprob);
+static void gemm_dispatch_mode(int mode, const Geom &g, const int32_t *order, const GemmProb &a, const GemmProb &b,
+                               int nprob, hipStream_t st) {
+    dim3 grid((unsigned)g.nb * g.nb * nprob);
     dim3 block(TileCfg<T, B>::NT);
     if (mode == MODE_NSX)
-        hipLaunchKernelGGL((k_leaf_gemm<T, B, MODE_NSX>), grid, block, 0, st, a, b, g);
+        hipLaunchKernelGGL((k_leaf_gemm<T, B, MODE_NSX>), grid, block, 0, st, a, b, g, order);
     else
-        hipLaunchKernelGGL((k_leaf_gemm<T, B, MODE_PLAIN>), grid, block, 0, st, a, b, g);
+        hipLaunchKernelGGL((k_leaf_gemm<T, B, MODE_PLAIN>), grid, block, 0, st, a, b, g, order);
 }
 
 template <typename T>
-static void gemm_dispatch_b(int mode, const Geom &g, const GemmProb &a, const GemmProb &b, int nprob,
-                            hipStream_t st) {
+static void gemm_dispatch_b(int mode, const Geom &g, const int32_t *order, const GemmProb &a, const GemmProb &b,
+                            int nprob, hipStream_t st) {
     if (g.b == 64)
-        gemm_dispatch_mode<T, 64>(mode, g, a, b, nprob, st);
+        gemm_dispatch_mode<T, 64>(mode, g, order, a, b, nprob, st);
     else if (g.b == 32)
-        gemm_dispatch_mode<T, 32>(mode, g, a, b, nprob, st);
+        gemm_dispatch_mode<T, 32>(mode, g, order, a, b, nprob, st);
     else
-        gemm_dispatch_mode<T, 16>(mode, g, a, b, nprob, st);
+        gemm_dispatch_mode<T, 16>(mode, g, order, a, b, nprob, st);
 }
 
-hipError_t launch_gemm(int prec, int mode, const Geom &g, const GemmProb *probs, int nprob, hipStream_t st) {
+hipError_t launch_gemm(int prec, int mode, const Geom &g, const int32_t *order, const GemmProb *probs, int nprob,
+                       hipStream_t st) {
     const GemmProb p1 = nprob > 1 ? probs[1] : probs[0];
     if (prec == P_F64)
-        gemm_dispatch_b<double>(mode, g, probs[0], p1, nprob, st);
+        gemm_dispatch_b<double>(mode, g, order, probs[0], p1, nprob, st);
     else
-        gemm_dispatch_b<float>(mode, g, probs[0], p1, nprob, st);
+        gemm_dispatch_b<float>(mode, g, order, probs[0], p1, nprob, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Longest-first dispatch: counting sort of the (problem, tile) work items by
+// decreasing retained count.  Workgroups are handed out in launch order, so
+// the heaviest tiles start first and the tail of the launch is short tiles.
+// The order inside a bucket is whatever the atomics give; the products do
+// not depend on it.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_lpt_order(const int32_t *__restrict__ cnt0,
+                                                     const int32_t *__restrict__ cnt1, int nprob, int nb,
+                                                     const int32_t *__restrict__ morton, int32_t *__restrict__ work) {
+    extern __shared__ int lds_hist[];  // nb + 1 bins
+    const int T = nb * nb;
+    const int items = nprob * T;
+    for (int c = threadIdx.x; c <= nb; c += 1024) lds_hist[c] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < items; e += 1024) {
+        const int p = e / T, t = morton[e % T];
+        const int c = (p == 0 ? cnt0 : cnt1)[t];
+        atomicAdd(&lds_hist[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int c = nb; c >= 0; --c) {
+            const int h = lds_hist[c];
+            lds_hist[c] = run;
+            run += h;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < items; e += 1024) {
+        const int p = e / T, t = morton[e % T];
+        const int c = (p == 0 ? cnt0 : cnt1)[t];
+        const int pos = atomicAdd(&lds_hist[c], 1);
+        work[pos] = p * T + t;
+    }
+}
+
+hipError_t launch_lpt_order(const Geom &g, const int32_t *cnt0, const int32_t *cnt1, int nprob,
+                            const int32_t *morton, int32_t *work, hipStream_t st) {
+    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), (g.nb + 1) * sizeof(int), st, cnt0,
+                       nprob > 1 ? cnt1 : cnt0, nprob, g.nb, morton, work);
     return hipGetLastError();
 }
 
