@@ -87,12 +87,16 @@ def main():
         infos.append(info)
         r, t, nR = ctx.ns_history()
         g = ctx.profile_read(spamm.KIND_GEMM)
+        # launches alternate x product / (y, z) update per enqueued iteration;
+        # those after the solve stopped do no work (and still count as time)
+        kfin = len(nR) - 1
         fl = []
-        for k in range(len(nR)):
-            fl.append(2.0 * leaf ** 3 * nR[k, 0])
-            if k < len(nR) - 1:
-                fl.append(2.0 * leaf ** 3 * (nR[k, 1] + nR[k, 2]))
-        assert len(fl) == len(g), (len(fl), len(g))
+        for L in range(len(g)):
+            it, upd = divmod(L, 2)
+            if upd == 0:
+                fl.append(2.0 * leaf ** 3 * nR[it, 0] if it <= kfin else 0.0)
+            else:
+                fl.append(2.0 * leaf ** 3 * (nR[it, 1] + nR[it, 2]) if it < kfin else 0.0)
         gemm_ms.extend(g.tolist())
         gemm_flops.extend(fl)
         cull_ms.extend(ctx.profile_read(spamm.KIND_CULL).tolist())

@@ -150,7 +150,44 @@ typedef struct {
 int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, int64_t ld, double tau,
             double tol, int maxit, const spamm_ns_opts *opts, spamm_ns_result *res, void *stream);
 
-/* Per-iteration record of the most recent ns_sqrt on this context, HOST
+/*
+ * Step API: the same dual-channel iteration as ns_sqrt, advanced explicitly so
+ * that many solves share launches (batched solves of uneven n) and solves
+ * can join and leave between steps (continuous batching for serving).
+ * ns_sqrt is spamm_solve_begin + spamm_solve_step until done +
+ * spamm_solve_finish, so results are identical whichever way a solve runs.
+ */
+typedef struct spamm_solve spamm_solve;
+
+/* Device bytes one solve holds from begin to finish (for admission control):
+ * five b x b-tiled iterates (y, y', z, z', h) in the leaf precision, five norm
+ * pyramids, three task lists of ceil(n/b)^3 int32, per-tile partials and the
+ * per-iteration records.  0 on bad arguments. */
+size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit);
+
+/* Checks s (as ns_sqrt), scales it, allocates the solve's device memory and
+ * sets y_0 = s', z_0 = I_n.  s may be freed once this returns (synchronises).
+ * *out receives the solve; errors as ns_sqrt (EINVAL, ENOMEM, EHIP). */
+int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, double tau, double tol, int maxit,
+                      const spamm_ns_opts *opts, spamm_solve **out, void *stream);
+
+/* Advances every running solve in solves[0..count) by `iterations` (>= 1)
+ * iterations: each iteration of all of them is one shared sequence of
+ * launches per (precision, leaf) group; the stop tests run on the device.
+ * Finished solves in the list are skipped.  Synchronises once.  Returns the
+ * number of solves of the list still running, or < 0 on error. */
+int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int iterations, void *stream);
+
+/* Host-side state after the last step: *done = 1 once stopped; res as for
+ * ns_sqrt.  Returns SPAMM_OK while running, else the solve's final status. */
+int spamm_solve_poll(spamm_solve *solve, int *done, spamm_ns_result *res);
+
+/* Writes Y = sqrt(c) y_k and Z = z_k / sqrt(c) (either may be NULL), records
+ * the solve's history for spamm_ns_history, frees the solve and returns its
+ * status (NOT_CONVERGED if it was still running).  Synchronises. */
+int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *solve, double *Y, double *Z, int64_t ld, void *stream);
+
+/* Per-iteration record of the most recent finished solve on this context, HOST
  * outputs of capacity cap entries: r[k], t[k] and nR[3k..3k+2] = |R| of x_k,
  * y_{k+1}, z_{k+1} (the last two are 0 where no update followed).  Returns the
  * number of entries available (iterations + 1), or < 0 on error. */

@@ -1,5 +1,12 @@
-// C-ABI entry points: argument validation, scratch management and the
-// orchestration of the kernels for SpAMM products and Newton-Schulz solves.
+// C-ABI entry points and the Newton-Schulz solve engine.
+//
+// A solve owns one device arena (its iterates, norm pyramids, task lists,
+// records and its device-side state).  Solves are advanced in steps: every
+// iteration of every solve of a step is enqueued as a fixed sequence of
+// batched launches over product tables (cull, longest-first plan, leaf
+// products, stop decision, pyramid; the same for the (y, z) update), and the
+// stop decision is taken on the device, so the host synchronises once per
+// step, not once per product.  ns_sqrt is begin + steps + finish.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,30 +42,40 @@ int fail(int code, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(SPAMM_EHIP, "%s failed: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-#define TRY(x)                     \
-    do {                           \
-        int s_ = (x);              \
-        if (s_ < 0) return s_;     \
+#define TRY(x)                 \
+    do {                       \
+        int s_ = (x);          \
+        if (s_ < 0) return s_; \
     } while (0)
 
 bool valid_leaf(int b) { return b == 16 || b == 32 || b == 64; }
 bool valid_prec(int p) { return p == SPAMM_F64 || p == SPAMM_F32 || p == SPAMM_BF16X3; }
 size_t elt_size(int prec) { return prec == SPAMM_F64 ? 8 : 4; }
+int kernel_prec(int prec) { return prec == SPAMM_F64 ? P_F64 : P_F32; }
+constexpr int MAX_NB = 1024;  // the pyramid's two passes cover P <= 1024
 
-// Named scratch slots owned by a context.
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over one device allocation (256-byte aligned pieces).
+struct Carve {
+    char *base;
+    size_t off;
+    template <typename T>
+    T *take(size_t count) {
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += (size_t)round_up((int64_t)(count * sizeof(T)), 256);
+        return p;
+    }
+};
+
+// Scratch slots of a context (spamm_norms / spamm_multiply / solve set-up).
 enum Slot {
-    S_T0, S_T1, S_T2, S_T3, S_T4,      // tiles
-    S_Q0, S_Q1, S_Q2, S_Q3, S_Q4,      // squared-norm pyramids
-    S_N0, S_N1, S_N2, S_N3, S_N4,      // leaf norms
-    S_CNT0, S_CNT1, S_CNT2,            // per-tile retained counts
-    S_KIDX0, S_KIDX1, S_KIDX2,         // per-tile retained-k lists
-    S_PART,                            // per-tile NS partial sums
-    S_CHECK,                           // input-check partials / column sums
-    S_SCAL,                            // device scalars
-    S_HIST_R, S_HIST_T, S_HIST_NR,     // per-iteration records
-    S_OFFS,                            // triple export offsets
-    S_ORDER,                           // Morton order of output tiles
-    S_WORK,                            // longest-first work list of one launch
+    S_T0, S_T1, S_T2,          // tiles
+    S_Q0, S_Q1, S_Q2,          // squared-norm pyramids
+    S_N0, S_N1, S_N2,          // leaf norms
+    S_CNT, S_KIDX,             // task list of the product
+    S_CHECK, S_SCAL, S_OFFS,   // input checks, device scalars, triple offsets
+    S_TAB,                     // product table of a multiply
     S_COUNT
 };
 
@@ -69,23 +86,81 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
+// Device tables for one ordered set of solves of one (precision, leaf).
+struct Plan {
+    std::vector<unsigned long long> ids;
+    int prec = 0, leaf = 0;
+    char *mem = nullptr;
+    size_t cap = 0;
+    ProdTable tx{}, tyz{};
+    SolveDesc *solves = nullptr;
+    SolveState *gather = nullptr;
+    SolveState *gather_host = nullptr;  // pinned
+    int nsolve = 0;
+    unsigned long long last_use = 0;
+};
+
 struct spamm_ctx {
     int device = 0;
     void *buf[S_COUNT] = {};
     size_t cap[S_COUNT] = {};
-    double *pinned = nullptr;  // 64 doubles of pinned host memory
-    int order_nb = -1;         // nb for which S_ORDER holds the tile order
-    std::vector<double> hist_r, hist_t;
+    double *pinned = nullptr;            // 64 doubles of pinned host memory
+    std::vector<double> hist_r, hist_t;  // records of the last finished solve
     std::vector<int64_t> hist_nR;
-    // launch timing
     bool prof = false;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     std::vector<ProfRec> recs;
+    std::vector<Plan *> plans;
+    unsigned long long next_id = 1, use_clock = 0;
+};
+
+struct spamm_solve {
+    spamm_ctx *ctx;
+    unsigned long long id;
+    Geom g;
+    int prec;
+    double tau, tau_s, tol, mu, c;
+    int maxit, stagnation;
+    char *mem;
+    size_t bytes;
+    void *y[2], *z[2], *h;
+    double *qy[2], *qz[2], *qh, *ny[2], *nz[2], *nh;
+    int32_t *cnt[3], *kidx[3];
+    double *part, *hist_r, *hist_t;
+    int64_t *hist_nR;
+    SolveState *state;
+    SolveState host_state;
 };
 
 namespace {
 
+// ---- measurement hooks -----------------------------------------------------
+enum { K_GEMM = 0, K_CULL = 1, K_PYR = 2, K_NKINDS = 3 };
+constexpr size_t PROF_POOL = 16384;
+
+hipEvent_t prof_begin(spamm_ctx *ctx, hipStream_t st) {
+    if (!ctx->prof || ctx->pool_used + 2 > ctx->pool.size()) return nullptr;
+    hipEvent_t a = ctx->pool[ctx->pool_used++];
+    if (hipEventRecord(a, st) != hipSuccess) return nullptr;
+    return a;
+}
+
+void prof_end(spamm_ctx *ctx, hipStream_t st, int kind, hipEvent_t a) {
+    if (!a) return;
+    hipEvent_t b = ctx->pool[ctx->pool_used++];
+    if (hipEventRecord(b, st) != hipSuccess) return;
+    ctx->recs.push_back(ProfRec{kind, a, b});
+}
+
+#define TIMED(kind, call)                     \
+    do {                                      \
+        hipEvent_t ev_ = prof_begin(ctx, st); \
+        HIPCHK(call);                         \
+        prof_end(ctx, st, kind, ev_);         \
+    } while (0)
+
+// ---- context scratch -------------------------------------------------------
 int ensure(spamm_ctx *ctx, int slot, size_t bytes) {
     if (bytes == 0) bytes = 256;
     if (ctx->cap[slot] >= bytes) return SPAMM_OK;
@@ -116,114 +191,6 @@ int enter(spamm_ctx *ctx) {
     return SPAMM_OK;
 }
 
-// Scratch for `nmat` operands (tiles, pyramids, leaf norms) and `nlist` task lists.
-int ensure_mats(spamm_ctx *ctx, const Geom &g, int prec, int nmat, int nlist) {
-    const size_t tiles = (size_t)g.nb * g.nb * g.b * g.b * elt_size(prec);
-    const size_t pyr = (size_t)pyr_len(g.P) * sizeof(double);
-    const size_t nrm = (size_t)g.nb * g.nb * sizeof(double);
-    for (int m = 0; m < nmat; ++m) {
-        TRY(ensure(ctx, S_T0 + m, tiles));
-        TRY(ensure(ctx, S_Q0 + m, pyr));
-        TRY(ensure(ctx, S_N0 + m, nrm));
-    }
-    const size_t cnt = (size_t)g.nb * g.nb * sizeof(int32_t);
-    const size_t kidx = (size_t)g.nb * g.nb * g.nb * sizeof(int32_t);
-    for (int l = 0; l < nlist; ++l) {
-        TRY(ensure(ctx, S_CNT0 + l, cnt));
-        TRY(ensure(ctx, S_KIDX0 + l, kidx));
-    }
-    TRY(ensure(ctx, S_SCAL, 64 * sizeof(double)));
-    if (ctx->order_nb != g.nb) {
-        TRY(ensure(ctx, S_ORDER, (size_t)g.nb * g.nb * sizeof(int32_t)));
-        std::vector<int32_t> order((size_t)g.nb * g.nb);
-        tile_order(g.nb, order.data());
-        HIPCHK(hipMemcpy(ctx->buf[S_ORDER], order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        ctx->order_nb = g.nb;
-    }
-    TRY(ensure(ctx, S_WORK, (size_t)2 * g.nb * g.nb * sizeof(int32_t)));
-    return SPAMM_OK;
-}
-
-enum { K_GEMM = 0, K_CULL = 1, K_PYR = 2, K_NKINDS = 3 };
-constexpr size_t PROF_POOL = 16384;
-
-// Records the opening event of a timed launch; returns nullptr when not timing.
-hipEvent_t prof_begin(spamm_ctx *ctx, hipStream_t st) {
-    if (!ctx->prof || ctx->pool_used + 2 > ctx->pool.size()) return nullptr;
-    hipEvent_t a = ctx->pool[ctx->pool_used++];
-    if (hipEventRecord(a, st) != hipSuccess) return nullptr;
-    return a;
-}
-
-void prof_end(spamm_ctx *ctx, hipStream_t st, int kind, hipEvent_t a) {
-    if (!a) return;
-    hipEvent_t b = ctx->pool[ctx->pool_used++];
-    if (hipEventRecord(b, st) != hipSuccess) return;
-    ctx->recs.push_back(ProfRec{kind, a, b});
-}
-
-#define TIMED(kind, call)                              \
-    do {                                               \
-        hipEvent_t ev_ = prof_begin(ctx, st);          \
-        HIPCHK(call);                                  \
-        prof_end(ctx, st, kind, ev_);                  \
-    } while (0)
-
-const int32_t *order_of(spamm_ctx *ctx) { return slot_ptr<int32_t>(ctx, S_ORDER); }
-
-// Longest-first work list for the products whose counts are in `probs`.
-hipError_t plan_gemm(spamm_ctx *ctx, const Geom &g, const GemmProb *probs, int nprob, hipStream_t st) {
-    return launch_lpt_order(g, probs[0].cnt, nprob > 1 ? probs[1].cnt : probs[0].cnt, nprob, order_of(ctx),
-                            slot_ptr<int32_t>(ctx, S_WORK), st);
-}
-const int32_t *work_of(spamm_ctx *ctx) { return slot_ptr<int32_t>(ctx, S_WORK); }
-
-Mat mat_of(spamm_ctx *ctx, int m) {
-    Mat x;
-    x.tiles = ctx->buf[S_T0 + m];
-    x.q = slot_ptr<double>(ctx, S_Q0 + m);
-    x.nrm = slot_ptr<double>(ctx, S_N0 + m);
-    return x;
-}
-
-const double *root_q(const Geom &g, const Mat &m) { return m.q + level_off(g.P, 1); }
-
-// Virtual blocks of the padded tree (index >= nb on the leaf level) are never
-// written by any kernel; they must read as zero norm.
-hipError_t zero_leaf_levels(spamm_ctx *ctx, const Geom &g, int nmat, hipStream_t st) {
-    for (int m = 0; m < nmat; ++m) {
-        hipError_t e = hipMemsetAsync(ctx->buf[S_Q0 + m], 0, (size_t)g.P * g.P * sizeof(double), st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-CullProb cull_prob(const Geom &g, const Mat &a, const Mat &b, double tau, spamm_ctx *ctx, int list) {
-    CullProb p;
-    p.nrmA = a.nrm;
-    p.nrmB = b.nrm;
-    p.rootA = root_q(g, a);
-    p.rootB = root_q(g, b);
-    p.tau = tau;
-    p.cnt = slot_ptr<int32_t>(ctx, S_CNT0 + list);
-    p.kidx = slot_ptr<int32_t>(ctx, S_KIDX0 + list);
-    return p;
-}
-
-GemmProb gemm_prob(const Mat &a, const Mat &b, const Mat &c, spamm_ctx *ctx, int list, double *part) {
-    GemmProb p;
-    p.A = a.tiles;
-    p.B = b.tiles;
-    p.C = c.tiles;
-    p.cnt = slot_ptr<int32_t>(ctx, S_CNT0 + list);
-    p.kidx = slot_ptr<int32_t>(ctx, S_KIDX0 + list);
-    p.qC = c.q;
-    p.part = part;
-    return p;
-}
-
-int kernel_prec(int prec) { return prec == SPAMM_F64 ? P_F64 : P_F32; }
-
 int validate_common(spamm_ctx *ctx, const void *A, int64_t n, int64_t ld, int leaf) {
     if (!ctx) return fail(SPAMM_EINVAL, "NULL context");
     if (!A) return fail(SPAMM_EINVAL, "NULL matrix pointer");
@@ -231,8 +198,344 @@ int validate_common(spamm_ctx *ctx, const void *A, int64_t n, int64_t ld, int le
     if (ld < n) return fail(SPAMM_EINVAL, "ld (%lld) < n (%lld)", (long long)ld, (long long)n);
     if (!valid_leaf(leaf)) return fail(SPAMM_EINVAL, "leaf must be 16, 32 or 64 (got %d)", leaf);
     const int64_t nb = (n + leaf - 1) / leaf;
-    if (nb > 2048) return fail(SPAMM_EINVAL, "n/leaf too large (%lld blocks per side)", (long long)nb);
+    if (nb > MAX_NB)
+        return fail(SPAMM_EINVAL, "n/leaf too large (%lld blocks per side, at most %d)", (long long)nb, MAX_NB);
     return SPAMM_OK;
+}
+
+// ---- product tables ----------------------------------------------------------
+struct TableSizes {
+    int nprod, total_cull, total_tiles, total_pyr, total_pyr2, max_nb, hist_blocks;
+};
+
+TableSizes table_sizes(const std::vector<ProdDesc> &prods) {
+    TableSizes z{(int)prods.size(), 0, 0, 0, 0, 0, 0};
+    for (const ProdDesc &d : prods) {
+        z.total_cull += (d.nb * d.nb + 3) / 4;
+        z.total_tiles += d.nb * d.nb;
+        z.total_pyr += d.P <= 32 ? 1 : (d.P / 32) * (d.P / 32);
+        z.total_pyr2 += d.P > 32 ? 1 : 0;
+        z.max_nb = std::max(z.max_nb, d.nb);
+    }
+    z.hist_blocks = z.total_tiles <= 16384 ? 0 : std::min(1024, (z.total_tiles + 4095) / 4096);
+    return z;
+}
+
+// Lays out one table in `c` (device addresses) and, when `host` is non-null,
+// writes its contents into the host staging image at the same offsets.
+ProdTable layout_table(Carve &c, const std::vector<ProdDesc> &prods, std::vector<char> *host) {
+    const TableSizes z = table_sizes(prods);
+    ProdTable t{};
+    const size_t o_prods = c.off;
+    t.prods = c.take<ProdDesc>(z.nprod);
+    const size_t o_cull = c.off;
+    t.cull_pre = c.take<int32_t>(z.nprod + 1);
+    const size_t o_tile = c.off;
+    t.tile_pre = c.take<int32_t>(z.nprod + 1);
+    const size_t o_pyr = c.off;
+    t.pyr_pre = c.take<int32_t>(z.nprod + 1);
+    const size_t o_pyr2 = c.off;
+    t.pyr2_pre = c.take<int32_t>(z.nprod + 1);
+    const size_t o_mort = c.off;
+    t.morton = c.take<int32_t>(z.total_tiles);
+    t.work = c.take<int32_t>(z.total_tiles);
+    t.jobs = c.take<Job>(z.total_tiles);
+    t.work_count = c.take<int32_t>(1);
+    t.hist = c.take<int32_t>((size_t)NBUCKET * std::max(z.hist_blocks, 1));
+    t.nprod = z.nprod;
+    t.hist_blocks = z.hist_blocks;
+    t.total_cull = z.total_cull;
+    t.total_tiles = z.total_tiles;
+    t.total_pyr = z.total_pyr;
+    t.total_pyr2 = z.total_pyr2;
+    t.max_nb = z.max_nb;
+    if (host) {
+        if (host->size() < c.off) host->resize(c.off);
+        char *h = host->data();
+        std::memcpy(h + o_prods, prods.data(), prods.size() * sizeof(ProdDesc));
+        int32_t *cull = (int32_t *)(h + o_cull), *tile = (int32_t *)(h + o_tile);
+        int32_t *pyr = (int32_t *)(h + o_pyr), *pyr2 = (int32_t *)(h + o_pyr2);
+        int32_t *mort = (int32_t *)(h + o_mort);
+        cull[0] = tile[0] = pyr[0] = pyr2[0] = 0;
+        for (int p = 0; p < z.nprod; ++p) {
+            const ProdDesc &d = prods[p];
+            cull[p + 1] = cull[p] + (d.nb * d.nb + 3) / 4;
+            tile[p + 1] = tile[p] + d.nb * d.nb;
+            pyr[p + 1] = pyr[p] + (d.P <= 32 ? 1 : (d.P / 32) * (d.P / 32));
+            pyr2[p + 1] = pyr2[p] + (d.P > 32 ? 1 : 0);
+            tile_order(d.nb, mort + tile[p]);
+        }
+    }
+    return t;
+}
+
+const double *root_of(const double *q, int P) { return q + level_off(P, 1); }
+
+ProdDesc x_product(const spamm_solve *s) {
+    ProdDesc d{};
+    d.n = s->g.n;
+    d.nb = s->g.nb;
+    d.P = s->g.P;
+    d.tau = s->tau;
+    for (int q = 0; q < 2; ++q) {
+        d.A[q] = s->y[q];
+        d.B[q] = s->z[q];
+        d.C[q] = s->h;
+        d.nrmA[q] = s->ny[q];
+        d.nrmB[q] = s->nz[q];
+        d.rootA[q] = root_of(s->qy[q], s->g.P);
+        d.rootB[q] = root_of(s->qz[q], s->g.P);
+        d.qC[q] = s->qh;
+        d.nrmC[q] = s->nh;
+    }
+    d.cnt = s->cnt[0];
+    d.kidx = s->kidx[0];
+    d.part = s->part;
+    d.state = s->state;
+    return d;
+}
+
+// y' = h (x)_{tau_s} y  (which = 0)  or  z' = z (x)_tau h  (which = 1)
+ProdDesc update_product(const spamm_solve *s, int which) {
+    ProdDesc d{};
+    d.n = s->g.n;
+    d.nb = s->g.nb;
+    d.P = s->g.P;
+    const double *rh = root_of(s->qh, s->g.P);
+    for (int q = 0; q < 2; ++q) {
+        if (which == 0) {
+            d.A[q] = s->h;
+            d.B[q] = s->y[q];
+            d.C[q] = s->y[q ^ 1];
+            d.nrmA[q] = s->nh;
+            d.nrmB[q] = s->ny[q];
+            d.rootA[q] = rh;
+            d.rootB[q] = root_of(s->qy[q], s->g.P);
+            d.qC[q] = s->qy[q ^ 1];
+            d.nrmC[q] = s->ny[q ^ 1];
+        } else {
+            d.A[q] = s->z[q];
+            d.B[q] = s->h;
+            d.C[q] = s->z[q ^ 1];
+            d.nrmA[q] = s->nz[q];
+            d.nrmB[q] = s->nh;
+            d.rootA[q] = root_of(s->qz[q], s->g.P);
+            d.rootB[q] = rh;
+            d.qC[q] = s->qz[q ^ 1];
+            d.nrmC[q] = s->nz[q ^ 1];
+        }
+    }
+    d.tau = which == 0 ? s->tau_s : s->tau;
+    d.cnt = s->cnt[1 + which];
+    d.kidx = s->kidx[1 + which];
+    d.part = nullptr;
+    d.state = s->state;
+    return d;
+}
+
+SolveDesc solve_desc(const spamm_solve *s) {
+    SolveDesc d{};
+    d.state = s->state;
+    d.n = s->g.n;
+    d.nb = s->g.nb;
+    d.maxit = s->maxit;
+    d.stagnation_stop = s->stagnation;
+    d.tol = s->tol;
+    d.part = s->part;
+    d.cnt_x = s->cnt[0];
+    d.cnt_y = s->cnt[1];
+    d.cnt_z = s->cnt[2];
+    d.hist_r = s->hist_r;
+    d.hist_t = s->hist_t;
+    d.hist_nR = s->hist_nR;
+    return d;
+}
+
+void free_plan(Plan *p) {
+    if (!p) return;
+    if (p->mem) (void)hipFree(p->mem);
+    if (p->gather_host) (void)hipHostFree(p->gather_host);
+    delete p;
+}
+
+// Drop cached tables that mention a solve (called when it finishes).
+void forget_solve(spamm_ctx *ctx, unsigned long long id) {
+    for (size_t i = 0; i < ctx->plans.size();) {
+        Plan *p = ctx->plans[i];
+        if (std::find(p->ids.begin(), p->ids.end(), id) != p->ids.end()) {
+            free_plan(p);
+            ctx->plans.erase(ctx->plans.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+// Tables for an ordered group of solves sharing (precision, leaf).
+int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_t st, Plan **out) {
+    std::vector<unsigned long long> ids;
+    for (spamm_solve *s : group) ids.push_back(s->id);
+    for (Plan *p : ctx->plans)
+        if (p->ids == ids) {
+            p->last_use = ++ctx->use_clock;
+            *out = p;
+            return SPAMM_OK;
+        }
+    std::vector<ProdDesc> px, pyz;
+    std::vector<SolveDesc> sd;
+    for (spamm_solve *s : group) {
+        px.push_back(x_product(s));
+        pyz.push_back(update_product(s, 0));
+        pyz.push_back(update_product(s, 1));
+        sd.push_back(solve_desc(s));
+    }
+    Carve sizing{nullptr, 0};
+    layout_table(sizing, px, nullptr);
+    layout_table(sizing, pyz, nullptr);
+    sizing.take<SolveDesc>(sd.size());
+    sizing.take<SolveState>(sd.size());
+    Plan *p = new Plan();
+    p->ids = ids;
+    p->prec = group[0]->prec;
+    p->leaf = group[0]->g.b;
+    p->nsolve = (int)group.size();
+    p->cap = sizing.off;
+    hipError_t e = hipMalloc((void **)&p->mem, p->cap);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&p->gather_host, sizeof(SolveState) * group.size(), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan(p);
+        return fail(SPAMM_ENOMEM, "table allocation failed: %s", hipGetErrorString(e));
+    }
+    std::vector<char> image;
+    Carve c{p->mem, 0};
+    p->tx = layout_table(c, px, &image);
+    p->tyz = layout_table(c, pyz, &image);
+    const size_t o_sd = c.off;
+    p->solves = c.take<SolveDesc>(sd.size());
+    p->gather = c.take<SolveState>(sd.size());
+    image.resize(c.off);
+    std::memcpy(image.data() + o_sd, sd.data(), sd.size() * sizeof(SolveDesc));
+    hipError_t ce = hipMemcpyAsync(p->mem, image.data(), image.size(), hipMemcpyHostToDevice, st);
+    if (ce == hipSuccess) ce = hipStreamSynchronize(st);  // the staging image must outlive the copy
+    if (ce != hipSuccess) {
+        free_plan(p);
+        return fail(SPAMM_EHIP, "table upload failed: %s", hipGetErrorString(ce));
+    }
+    p->last_use = ++ctx->use_clock;
+    if (ctx->plans.size() >= 8) {
+        auto lru = std::min_element(ctx->plans.begin(), ctx->plans.end(),
+                                    [](Plan *a, Plan *b) { return a->last_use < b->last_use; });
+        free_plan(*lru);
+        ctx->plans.erase(lru);
+    }
+    ctx->plans.push_back(p);
+    *out = p;
+    return SPAMM_OK;
+}
+
+// One Newton-Schulz iteration of every running solve of a plan.
+int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
+    const int kp = kernel_prec(p->prec);
+    TIMED(K_CULL, launch_cull_tab(p->tx, st));
+    HIPCHK(launch_plan_tab(p->tx, p->leaf, (int)elt_size(p->prec), st));
+    TIMED(K_GEMM, launch_gemm_tab(kp, p->leaf, p->tx, st));
+    HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
+    TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
+    TIMED(K_CULL, launch_cull_tab(p->tyz, st));
+    HIPCHK(launch_plan_tab(p->tyz, p->leaf, (int)elt_size(p->prec), st));
+    TIMED(K_GEMM, launch_gemm_tab(kp, p->leaf, p->tyz, st));
+    TIMED(K_PYR, launch_pyramid_tab(p->tyz, st));
+    HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
+    return SPAMM_OK;
+}
+
+// Arena layout of one solve; returns its size.  With s non-null, also sets
+// the solve's pointers into s->mem.
+size_t solve_bytes(const Geom &g, int prec, int maxit, spamm_solve *s) {
+    Carve c{s ? s->mem : nullptr, 0};
+    const size_t tiles = (size_t)g.nb * g.nb * g.b * g.b * elt_size(prec);
+    const size_t pyr = (size_t)pyr_len(g.P);
+    const size_t nb2 = (size_t)g.nb * g.nb;
+    void *tl[5];
+    for (int i = 0; i < 5; ++i) tl[i] = c.take<char>(tiles);
+    double *q[5], *nr[5];
+    for (int i = 0; i < 5; ++i) q[i] = c.take<double>(pyr);
+    for (int i = 0; i < 5; ++i) nr[i] = c.take<double>(2 * nb2);  // leaf norms and their transpose
+    int32_t *cnt[3], *kidx[3];
+    for (int i = 0; i < 3; ++i) cnt[i] = c.take<int32_t>(nb2);
+    for (int i = 0; i < 3; ++i) kidx[i] = c.take<int32_t>(nb2 * g.nb);
+    double *part = c.take<double>(2 * nb2);
+    double *hr = c.take<double>(maxit + 1);
+    double *ht = c.take<double>(maxit + 1);
+    int64_t *hn = c.take<int64_t>(3 * (size_t)(maxit + 1));
+    SolveState *state = c.take<SolveState>(1);
+    if (s) {
+        s->y[0] = tl[0];
+        s->y[1] = tl[1];
+        s->z[0] = tl[2];
+        s->z[1] = tl[3];
+        s->h = tl[4];
+        s->qy[0] = q[0];
+        s->qy[1] = q[1];
+        s->qz[0] = q[2];
+        s->qz[1] = q[3];
+        s->qh = q[4];
+        s->ny[0] = nr[0];
+        s->ny[1] = nr[1];
+        s->nz[0] = nr[2];
+        s->nz[1] = nr[3];
+        s->nh = nr[4];
+        for (int i = 0; i < 3; ++i) {
+            s->cnt[i] = cnt[i];
+            s->kidx[i] = kidx[i];
+        }
+        s->part = part;
+        s->hist_r = hr;
+        s->hist_t = ht;
+        s->hist_nR = hn;
+        s->state = state;
+    }
+    return c.off;
+}
+
+int validate_ns(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, double tau, double tol, int maxit,
+                const spamm_ns_opts &o) {
+    TRY(validate_common(ctx, s, n, ld, o.leaf));
+    if (!(tau >= 0.0) || std::isinf(tau)) return fail(SPAMM_EINVAL, "tau must be finite and >= 0");
+    if (!(tol > 0.0)) return fail(SPAMM_EINVAL, "tol must be > 0");
+    if (maxit < 0 || maxit > 100000) return fail(SPAMM_EINVAL, "maxit must be in [0, 100000]");
+    if (!valid_prec(o.prec)) return fail(SPAMM_EINVAL, "unknown precision %d", o.prec);
+    if (o.prec == SPAMM_BF16X3) return fail(SPAMM_EINVAL, "BF16x3 leaves are not available in this build");
+    if (!(o.mu_rel >= 0.0) || std::isinf(o.mu_rel)) return fail(SPAMM_EINVAL, "mu_rel must be finite and >= 0");
+    if (std::isnan(o.tau_s) || std::isinf(o.tau_s)) return fail(SPAMM_EINVAL, "tau_s must be finite");
+    return SPAMM_OK;
+}
+
+spamm_ns_opts default_opts(const spamm_ns_opts *opts) {
+    spamm_ns_opts o;
+    o.leaf = 32;
+    o.prec = SPAMM_F64;
+    o.tau_s = -1.0;
+    o.mu_rel = 0.0;
+    o.stagnation_stop = 0;
+    if (opts) {
+        o = *opts;
+        if (o.leaf == 0) o.leaf = 32;
+    }
+    return o;
+}
+
+void fill_result(const spamm_solve *s, spamm_ns_result *res) {
+    if (!res) return;
+    const SolveState &h = s->host_state;
+    res->iterations = h.k;
+    res->resid = h.r;
+    res->trace_err = h.t;
+    res->scale = s->c;
+    res->triples_total = h.triples;
+    res->flops_total = 2.0 * (double)s->g.b * s->g.b * s->g.b * (double)h.triples;
 }
 
 }  // namespace
@@ -263,6 +566,8 @@ int spamm_destroy(spamm_ctx *ctx) {
     if (!ctx) return SPAMM_OK;
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipDeviceSynchronize());
+    for (Plan *p : ctx->plans) free_plan(p);
+    ctx->plans.clear();
     for (hipEvent_t e : ctx->pool) HIPCHK(hipEventDestroy(e));
     for (int s = 0; s < S_COUNT; ++s)
         if (ctx->buf[s]) HIPCHK(hipFree(ctx->buf[s]));
@@ -284,14 +589,16 @@ int spamm_norms(spamm_ctx *ctx, const double *A, int64_t n, int64_t ld, int leaf
     TRY(enter(ctx));
     hipStream_t st = (hipStream_t)stream;
     const Geom g = make_geom(n, leaf);
-    TRY(ensure_mats(ctx, g, SPAMM_F64, 1, 0));
-    HIPCHK(zero_leaf_levels(ctx, g, 1, st));
-    Mat a = mat_of(ctx, 0);
-    HIPCHK(launch_ingest(P_F64, A, ld, 0.0, 1.0, g, a, st));
-    TIMED(K_PYR, launch_pyramid(g, a, st));
-    HIPCHK(launch_norms_out(g, a.q, pyramid, st));
+    TRY(ensure(ctx, S_T0, (size_t)g.nb * g.nb * g.b * g.b * sizeof(double)));
+    TRY(ensure(ctx, S_Q0, (size_t)pyr_len(g.P) * sizeof(double)));
+    TRY(ensure(ctx, S_N0, 2 * (size_t)g.nb * g.nb * sizeof(double)));
+    double *q = slot_ptr<double>(ctx, S_Q0), *nrm = slot_ptr<double>(ctx, S_N0);
+    HIPCHK(hipMemsetAsync(q, 0, (size_t)g.P * g.P * sizeof(double), st));  // virtual blocks read as 0
+    HIPCHK(launch_ingest(P_F64, A, ld, 0.0, 1.0, g, ctx->buf[S_T0], q, st));
+    TIMED(K_PYR, launch_pyramid(g, q, nrm, q, nrm, 1, st));
+    HIPCHK(launch_norms_out(g, q, pyramid, st));
     if (root_norm_host) {
-        HIPCHK(hipMemcpyAsync(ctx->pinned, root_q(g, a), sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(ctx->pinned, root_of(q, g.P), sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         *root_norm_host = std::sqrt(ctx->pinned[0]);
     }
@@ -311,27 +618,65 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     hipStream_t st = (hipStream_t)stream;
     const Geom g = make_geom(n, leaf);
     const int kp = kernel_prec(prec);
-    TRY(ensure_mats(ctx, g, prec, 3, 1));
-    HIPCHK(zero_leaf_levels(ctx, g, 3, st));
-    Mat a = mat_of(ctx, 0), b = mat_of(ctx, 1), c = mat_of(ctx, 2);
-    HIPCHK(launch_ingest(kp, A, ld, 0.0, 1.0, g, a, st));
-    HIPCHK(launch_ingest(kp, B, ld, 0.0, 1.0, g, b, st));
-    TIMED(K_PYR, launch_pyramid2(g, a, b, st));
-    CullProb cp = cull_prob(g, a, b, tau, ctx, 0);
-    TIMED(K_CULL, launch_cull(g, &cp, 1, st));
-    GemmProb gp = gemm_prob(a, b, c, ctx, 0, nullptr);
-    HIPCHK(plan_gemm(ctx, g, &gp, 1, st));
-    TIMED(K_GEMM, launch_gemm(kp, MODE_PLAIN, g, work_of(ctx), &gp, 1, st));
-    HIPCHK(launch_egress(kp, g, c.tiles, C, ld, 1.0, 0, st));
+    const size_t nb2 = (size_t)g.nb * g.nb;
+    for (int m = 0; m < 3; ++m) {
+        TRY(ensure(ctx, S_T0 + m, nb2 * g.b * g.b * elt_size(prec)));
+        TRY(ensure(ctx, S_Q0 + m, (size_t)pyr_len(g.P) * sizeof(double)));
+        TRY(ensure(ctx, S_N0 + m, 2 * nb2 * sizeof(double)));
+    }
+    TRY(ensure(ctx, S_CNT, nb2 * sizeof(int32_t)));
+    TRY(ensure(ctx, S_KIDX, nb2 * g.nb * sizeof(int32_t)));
+    TRY(ensure(ctx, S_SCAL, 64 * sizeof(double)));
+    double *q[3], *nr[3];
+    for (int m = 0; m < 3; ++m) {
+        q[m] = slot_ptr<double>(ctx, S_Q0 + m);
+        nr[m] = slot_ptr<double>(ctx, S_N0 + m);
+        HIPCHK(hipMemsetAsync(q[m], 0, (size_t)g.P * g.P * sizeof(double), st));
+    }
+    HIPCHK(launch_ingest(kp, A, ld, 0.0, 1.0, g, ctx->buf[S_T0], q[0], st));
+    HIPCHK(launch_ingest(kp, B, ld, 0.0, 1.0, g, ctx->buf[S_T1], q[1], st));
+    TIMED(K_PYR, launch_pyramid(g, q[0], nr[0], q[1], nr[1], 2, st));
+
+    ProdDesc d{};
+    d.n = n;
+    d.nb = g.nb;
+    d.P = g.P;
+    d.tau = tau;
+    d.A[0] = d.A[1] = ctx->buf[S_T0];
+    d.B[0] = d.B[1] = ctx->buf[S_T1];
+    d.C[0] = d.C[1] = ctx->buf[S_T2];
+    d.nrmA[0] = d.nrmA[1] = nr[0];
+    d.nrmB[0] = d.nrmB[1] = nr[1];
+    d.rootA[0] = d.rootA[1] = root_of(q[0], g.P);
+    d.rootB[0] = d.rootB[1] = root_of(q[1], g.P);
+    d.qC[0] = d.qC[1] = q[2];
+    d.nrmC[0] = d.nrmC[1] = nr[2];
+    d.cnt = slot_ptr<int32_t>(ctx, S_CNT);
+    d.kidx = slot_ptr<int32_t>(ctx, S_KIDX);
+    d.part = nullptr;
+    d.state = nullptr;
+    std::vector<ProdDesc> prods{d};
+    Carve sizing{nullptr, 0};
+    layout_table(sizing, prods, nullptr);
+    TRY(ensure(ctx, S_TAB, sizing.off));
+    std::vector<char> image;
+    Carve c{(char *)ctx->buf[S_TAB], 0};
+    ProdTable t = layout_table(c, prods, &image);
+    image.resize(c.off);
+    HIPCHK(hipMemcpyAsync(ctx->buf[S_TAB], image.data(), image.size(), hipMemcpyHostToDevice, st));
+    TIMED(K_CULL, launch_cull_tab(t, st));
+    HIPCHK(launch_plan_tab(t, leaf, (int)elt_size(prec), st));
+    TIMED(K_GEMM, launch_gemm_tab(kp, leaf, t, st));
+    HIPCHK(launch_egress(kp, g, ctx->buf[S_T2], C, ld, 1.0, 0, st));
     int status = SPAMM_OK;
     if (stats || triples) {
-        TRY(ensure(ctx, S_OFFS, (size_t)g.nb * g.nb * sizeof(int64_t)));
+        TRY(ensure(ctx, S_OFFS, nb2 * sizeof(int64_t)));
         int64_t *offs = slot_ptr<int64_t>(ctx, S_OFFS);
         int64_t *total = reinterpret_cast<int64_t *>(slot_ptr<double>(ctx, S_SCAL) + 8);
-        HIPCHK(launch_count_triples(g, cp.cnt, offs, total, st));
+        HIPCHK(launch_count_triples(g, d.cnt, offs, total, st));
         HIPCHK(hipMemcpyAsync(ctx->pinned, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(ctx->pinned + 1, cp.rootA, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(ctx->pinned + 2, cp.rootB, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(ctx->pinned + 1, d.rootA[0], sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(ctx->pinned + 2, d.rootB[0], sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         int64_t retained;
         std::memcpy(&retained, ctx->pinned, sizeof(int64_t));
@@ -339,10 +684,8 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
             if (retained > cap)
                 status = fail(SPAMM_ECAPACITY, "|R| = %lld exceeds triple capacity %lld", (long long)retained,
                               (long long)cap);
-            else {
-                HIPCHK(launch_write_triples(g, cp.cnt, cp.kidx, offs, triples, st));
-                HIPCHK(hipStreamSynchronize(st));
-            }
+            else
+                HIPCHK(launch_write_triples(g, d.cnt, d.kidx, offs, triples, st));
         }
         if (stats) {
             stats->retained = retained;
@@ -351,53 +694,33 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
             stats->flops = 2.0 * (double)leaf * leaf * leaf * (double)retained;
         }
     }
+    // the host staging image must outlive its copy
+    HIPCHK(hipStreamSynchronize(st));
     return status;
 }
 
-int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, int64_t ld, double tau,
-            double tol, int maxit, const spamm_ns_opts *opts, spamm_ns_result *res, void *stream) {
-    spamm_ns_opts o;
-    o.leaf = 32;
-    o.prec = SPAMM_F64;
-    o.tau_s = -1.0;
-    o.mu_rel = 0.0;
-    o.stagnation_stop = 0;
-    if (opts) {
-        o = *opts;
-        if (o.leaf == 0) o.leaf = 32;
-    }
-    TRY(validate_common(ctx, s, n, ld, o.leaf));
-    if (!Y || !Z) return fail(SPAMM_EINVAL, "NULL output pointer");
-    if (!(tau >= 0.0) || std::isinf(tau)) return fail(SPAMM_EINVAL, "tau must be finite and >= 0");
-    if (!(tol > 0.0)) return fail(SPAMM_EINVAL, "tol must be > 0");
-    if (maxit < 0) return fail(SPAMM_EINVAL, "maxit must be >= 0");
-    if (!valid_prec(o.prec)) return fail(SPAMM_EINVAL, "unknown precision %d", o.prec);
-    if (o.prec == SPAMM_BF16X3) return fail(SPAMM_EINVAL, "BF16x3 leaves are not available in this build");
-    if (!(o.mu_rel >= 0.0) || std::isinf(o.mu_rel)) return fail(SPAMM_EINVAL, "mu_rel must be finite and >= 0");
-    if (std::isnan(o.tau_s) || std::isinf(o.tau_s)) return fail(SPAMM_EINVAL, "tau_s must be finite");
-    const double tau_s = o.tau_s < 0.0 ? tau : o.tau_s;
+size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit) {
+    if (n <= 0 || !valid_leaf(leaf) || !valid_prec(prec) || maxit < 0) return 0;
+    const Geom g = make_geom(n, leaf);
+    return solve_bytes(g, prec, maxit, nullptr);
+}
+
+int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, double tau, double tol, int maxit,
+                      const spamm_ns_opts *opts, spamm_solve **out, void *stream) {
+    if (!out) return fail(SPAMM_EINVAL, "NULL output handle");
+    *out = nullptr;
+    const spamm_ns_opts o = default_opts(opts);
+    TRY(validate_ns(ctx, s, n, ld, tau, tol, maxit, o));
     TRY(enter(ctx));
     hipStream_t st = (hipStream_t)stream;
     const Geom g = make_geom(n, o.leaf);
-    const int kp = kernel_prec(o.prec);
 
-    // operands: 0,1 = y (ping-pong), 2,3 = z (ping-pong), 4 = h; lists: 0 = x, 1 = y, 2 = z
-    TRY(ensure_mats(ctx, g, o.prec, 5, 3));
+    // input checks and the Gershgorin scale (context scratch, one read-back)
     const int64_t nbk = (n + 31) / 32;
     TRY(ensure(ctx, S_CHECK, (size_t)std::max<int64_t>(3 * nbk * nbk, n) * sizeof(double)));
-    TRY(ensure(ctx, S_PART, (size_t)2 * g.nb * g.nb * sizeof(double)));
-    TRY(ensure(ctx, S_HIST_R, (size_t)(maxit + 1) * sizeof(double)));
-    TRY(ensure(ctx, S_HIST_T, (size_t)(maxit + 1) * sizeof(double)));
-    TRY(ensure(ctx, S_HIST_NR, (size_t)3 * (maxit + 1) * sizeof(int64_t)));
-    double *scal = slot_ptr<double>(ctx, S_SCAL);
-    double *check = slot_ptr<double>(ctx, S_CHECK);
-    double *part = slot_ptr<double>(ctx, S_PART);
-    double *hist_r = slot_ptr<double>(ctx, S_HIST_R);
-    double *hist_t = slot_ptr<double>(ctx, S_HIST_T);
-    int64_t *hist_nR = slot_ptr<int64_t>(ctx, S_HIST_NR);
+    TRY(ensure(ctx, S_SCAL, 64 * sizeof(double)));
+    double *scal = slot_ptr<double>(ctx, S_SCAL), *check = slot_ptr<double>(ctx, S_CHECK);
     double *pin = ctx->pinned;
-
-    // input checks and the Gershgorin scale
     HIPCHK(launch_check_input(s, n, ld, check, scal, st));
     HIPCHK(launch_colsum_max(s, n, ld, 0.0, check, scal + 3, st));
     HIPCHK(hipMemcpyAsync(pin, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -415,86 +738,156 @@ int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, in
     }
     if (!(c > 0.0)) return fail(SPAMM_EINVAL, "s has a zero Gershgorin bound");
 
-    HIPCHK(hipMemsetAsync(hist_nR, 0, (size_t)3 * (maxit + 1) * sizeof(int64_t), st));
-    HIPCHK(zero_leaf_levels(ctx, g, 5, st));
-    int yi = 0, zi = 2;
-    Mat h = mat_of(ctx, 4);
-    HIPCHK(launch_ingest(kp, s, ld, mu, c, g, mat_of(ctx, yi), st));
-    HIPCHK(launch_identity(kp, g, mat_of(ctx, zi), st));
-    TIMED(K_PYR, launch_pyramid2(g, mat_of(ctx, yi), mat_of(ctx, zi), st));
-
-    int status = SPAMM_NOT_CONVERGED;
-    int k = 0;
-    double r0 = 0.0, r_prev = 0.0, r = 0.0, tk = 0.0;
-    int nondecrease = 0;
-    for (k = 0;; ++k) {
-        Mat y = mat_of(ctx, yi), z = mat_of(ctx, zi);
-        CullProb cx = cull_prob(g, y, z, tau, ctx, 0);
-        TIMED(K_CULL, launch_cull(g, &cx, 1, st));
-        GemmProb gx = gemm_prob(y, z, h, ctx, 0, part);
-        HIPCHK(plan_gemm(ctx, g, &gx, 1, st));
-        TIMED(K_GEMM, launch_gemm(kp, MODE_NSX, g, work_of(ctx), &gx, 1, st));
-        HIPCHK(launch_ns_reduce(g, part, cx.cnt, slot_ptr<int32_t>(ctx, S_CNT1), slot_ptr<int32_t>(ctx, S_CNT2), k,
-                                hist_r, hist_t, hist_nR, scal + 8, st));
-        TIMED(K_PYR, launch_pyramid(g, h, st));
-        HIPCHK(hipMemcpyAsync(pin, scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        r = pin[0];
-        tk = pin[1];
-        if (k == 0) r0 = r;
-        if (r < tol) {
-            status = SPAMM_OK;
-            break;
-        }
-        if (!std::isfinite(r) || r > 10.0 * std::fmax(r0, std::sqrt((double)n))) {
-            status = fail(SPAMM_EDIVERGED, "iteration diverged at k = %d (r = %g)", k, r);
-            break;
-        }
-        if (o.stagnation_stop && k > 0) {
-            nondecrease = (r >= 0.99 * r_prev) ? nondecrease + 1 : 0;
-            if (nondecrease >= 2) {
-                status = SPAMM_STAGNATED;
-                break;
-            }
-        }
-        r_prev = r;
-        if (k == maxit) {
-            status = SPAMM_NOT_CONVERGED;
-            break;
-        }
-        const int yn = yi ^ 1, zn = zi ^ 1;
-        Mat ynm = mat_of(ctx, yn), znm = mat_of(ctx, zn);
-        CullProb cu[2] = {cull_prob(g, h, y, tau_s, ctx, 1), cull_prob(g, z, h, tau, ctx, 2)};
-        TIMED(K_CULL, launch_cull(g, cu, 2, st));
-        GemmProb gu[2] = {gemm_prob(h, y, ynm, ctx, 1, nullptr), gemm_prob(z, h, znm, ctx, 2, nullptr)};
-        HIPCHK(plan_gemm(ctx, g, gu, 2, st));
-        TIMED(K_GEMM, launch_gemm(kp, MODE_PLAIN, g, work_of(ctx), gu, 2, st));
-        TIMED(K_PYR, launch_pyramid2(g, ynm, znm, st));
-        yi = yn;
-        zi = zn;
+    spamm_solve *sv = new spamm_solve();
+    sv->ctx = ctx;
+    sv->id = ctx->next_id++;
+    sv->g = g;
+    sv->prec = o.prec;
+    sv->tau = tau;
+    sv->tau_s = o.tau_s < 0.0 ? tau : o.tau_s;
+    sv->tol = tol;
+    sv->mu = mu;
+    sv->c = c;
+    sv->maxit = maxit;
+    sv->stagnation = o.stagnation_stop ? 1 : 0;
+    sv->mem = nullptr;
+    sv->bytes = solve_bytes(g, o.prec, maxit, nullptr);
+    hipError_t e = hipMalloc((void **)&sv->mem, sv->bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete sv;
+        return fail(SPAMM_ENOMEM, "solve allocation of %zu bytes failed: %s", (size_t)sv->bytes,
+                    hipGetErrorString(e));
     }
-    const double sc = std::sqrt(c);
-    HIPCHK(launch_egress(kp, g, mat_of(ctx, yi).tiles, Y, ld, sc, 0, st));
-    HIPCHK(launch_egress(kp, g, mat_of(ctx, zi).tiles, Z, ld, sc, 1, st));
+    solve_bytes(g, o.prec, maxit, sv);
+    const int kp = kernel_prec(o.prec);
+    const size_t leafq = (size_t)g.P * g.P * sizeof(double);
+    int rc = SPAMM_OK;
+    auto chk = [&](hipError_t err, const char *what) {
+        if (err != hipSuccess && rc == SPAMM_OK) rc = fail(SPAMM_EHIP, "%s failed: %s", what, hipGetErrorString(err));
+    };
+    // virtual blocks of every pyramid read as zero; records start empty
+    for (double *q : {sv->qy[0], sv->qy[1], sv->qz[0], sv->qz[1], sv->qh})
+        chk(hipMemsetAsync(q, 0, leafq, st), "memset");
+    chk(hipMemsetAsync(sv->hist_nR, 0, 3 * (size_t)(maxit + 1) * sizeof(int64_t), st), "memset");
+    chk(launch_ingest(kp, s, ld, mu, c, g, sv->y[0], sv->qy[0], st), "ingest");
+    chk(launch_identity(kp, g, sv->z[0], sv->qz[0], st), "identity");
+    chk(launch_pyramid(g, sv->qy[0], sv->ny[0], sv->qz[0], sv->nz[0], 2, st), "pyramid");
+    SolveState init{};
+    init.status = ST_RUNNING;
+    sv->host_state = init;
+    chk(hipMemcpyAsync(sv->state, &sv->host_state, sizeof(SolveState), hipMemcpyHostToDevice, st), "state");
+    chk(hipStreamSynchronize(st), "synchronise");
+    if (rc != SPAMM_OK) {
+        (void)hipFree(sv->mem);
+        delete sv;
+        return rc;
+    }
+    *out = sv;
+    return SPAMM_OK;
+}
+
+int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int iterations, void *stream) {
+    TRY(enter(ctx));
+    if (count < 0 || (count > 0 && !solves)) return fail(SPAMM_EINVAL, "bad solve list");
+    if (iterations < 1) return fail(SPAMM_EINVAL, "iterations must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    // running solves, grouped by (precision, leaf) in the caller's order
+    std::vector<std::vector<spamm_solve *>> groups;
+    for (int i = 0; i < count; ++i) {
+        spamm_solve *s = solves[i];
+        if (!s || s->ctx != ctx) return fail(SPAMM_EINVAL, "solve %d is NULL or belongs to another context", i);
+        for (int j = 0; j < i; ++j)
+            if (solves[j] == s) return fail(SPAMM_EINVAL, "solve %d appears twice", i);
+        if (s->host_state.status != ST_RUNNING) continue;
+        auto it = std::find_if(groups.begin(), groups.end(), [&](const std::vector<spamm_solve *> &gr) {
+            return gr[0]->prec == s->prec && gr[0]->g.b == s->g.b;
+        });
+        if (it == groups.end())
+            groups.push_back({s});
+        else
+            it->push_back(s);
+    }
+    if (groups.empty()) return 0;
+    std::vector<Plan *> plans;
+    for (auto &gr : groups) {
+        Plan *p = nullptr;
+        TRY(get_plan(ctx, gr, st, &p));
+        plans.push_back(p);
+    }
+    for (int it = 0; it < iterations; ++it)
+        for (Plan *p : plans) TRY(enqueue_iteration(ctx, p, st));
+    for (Plan *p : plans) {
+        HIPCHK(launch_gather_states(p->solves, p->nsolve, p->gather, st));
+        HIPCHK(hipMemcpyAsync(p->gather_host, p->gather, p->nsolve * sizeof(SolveState), hipMemcpyDeviceToHost,
+                              st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    int running = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (size_t i = 0; i < groups[gi].size(); ++i) {
+            groups[gi][i]->host_state = plans[gi]->gather_host[i];
+            if (groups[gi][i]->host_state.status == ST_RUNNING) ++running;
+        }
+    return running;
+}
+
+int spamm_solve_poll(spamm_solve *s, int *done, spamm_ns_result *res) {
+    if (!s) return fail(SPAMM_EINVAL, "NULL solve");
+    const int st = s->host_state.status;
+    if (done) *done = st != ST_RUNNING;
+    fill_result(s, res);
+    return st == ST_RUNNING ? SPAMM_OK : st;
+}
+
+int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *s, double *Y, double *Z, int64_t ld, void *stream) {
+    TRY(enter(ctx));
+    if (!s || s->ctx != ctx) return fail(SPAMM_EINVAL, "NULL solve or solve of another context");
+    if ((Y || Z) && ld < s->g.n)
+        return fail(SPAMM_EINVAL, "ld (%lld) < n (%lld)", (long long)ld, (long long)s->g.n);
+    hipStream_t st = (hipStream_t)stream;
+    const SolveState h = s->host_state;
+    const int status = h.status == ST_RUNNING ? SPAMM_NOT_CONVERGED : h.status;
+    const int kp = kernel_prec(s->prec);
+    const double sc = std::sqrt(s->c);
+    const int k = h.k;
+    if (Y) HIPCHK(launch_egress(kp, s->g, s->y[h.parity], Y, ld, sc, 0, st));
+    if (Z) HIPCHK(launch_egress(kp, s->g, s->z[h.parity], Z, ld, sc, 1, st));
     ctx->hist_r.assign(k + 1, 0.0);
     ctx->hist_t.assign(k + 1, 0.0);
     ctx->hist_nR.assign(3 * (size_t)(k + 1), 0);
-    HIPCHK(hipMemcpyAsync(ctx->hist_r.data(), hist_r, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ctx->hist_t.data(), hist_t, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ctx->hist_nR.data(), hist_nR, 3 * (k + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(ctx->hist_r.data(), s->hist_r, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->hist_t.data(), s->hist_t, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->hist_nR.data(), s->hist_nR, 3 * (k + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
                           st));
     HIPCHK(hipStreamSynchronize(st));
-    if (res) {
-        res->iterations = k;
-        res->resid = r;
-        res->trace_err = tk;
-        res->scale = c;
-        int64_t tot = 0;
-        for (int64_t v : ctx->hist_nR) tot += v;
-        res->triples_total = tot;
-        res->flops_total = 2.0 * (double)o.leaf * o.leaf * o.leaf * (double)tot;
-    }
+    forget_solve(ctx, s->id);
+    HIPCHK(hipFree(s->mem));
+    delete s;
+    if (status == SPAMM_EDIVERGED) return fail(SPAMM_EDIVERGED, "iteration diverged at k = %d (r = %g)", k, h.r);
     return status;
+}
+
+int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, int64_t ld, double tau,
+            double tol, int maxit, const spamm_ns_opts *opts, spamm_ns_result *res, void *stream) {
+    if (!Y || !Z) return fail(SPAMM_EINVAL, "NULL output pointer");
+    spamm_solve *sv = nullptr;
+    TRY(spamm_solve_begin(ctx, s, n, ld, tau, tol, maxit, opts, &sv, stream));
+    // a few iterations per synchronisation, so a finished solve wastes little
+    int rc = SPAMM_OK;
+    while (sv->host_state.status == ST_RUNNING) {
+        const int left = maxit + 1 - sv->host_state.k;
+        rc = spamm_solve_step(ctx, &sv, 1, std::max(1, std::min(4, left)), stream);
+        if (rc < 0) break;
+    }
+    fill_result(sv, res);
+    if (rc < 0) {
+        const std::string keep = g_err;
+        (void)spamm_solve_finish(ctx, sv, nullptr, nullptr, ld, stream);
+        g_err = keep;
+        return rc;
+    }
+    return spamm_solve_finish(ctx, sv, Y, Z, ld, stream);
 }
 
 int spamm_ns_history(spamm_ctx *ctx, double *r, double *t, int64_t *nR, int cap) {

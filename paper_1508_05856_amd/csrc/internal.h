@@ -1,4 +1,4 @@
-// Internal declarations shared by the kernels and the C-ABI host code.
+// Internal declarations shared by the kernels and the host engine.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,61 +26,107 @@ int64_t pyr_len(int P);
 int64_t level_off(int P, int S);
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
-enum GemmMode { MODE_PLAIN = 0, MODE_NSX = 1 };
 
-// One operand as held on the device between products.
-struct Mat {
-    void *tiles;   // nb*nb tiles of b*b elements, tile (i,k) at (i*nb+k)*b*b, row-major inside
-    double *q;     // squared-norm pyramid, leaves first (P*P), root last
-    double *nrm;   // nb*nb leaf norms sqrt(q) for the cull, row-major (i,k)
-};
-
-// Cull of one product C = A (x)_tau B into per-tile retained-k lists.
-struct CullProb {
-    const double *nrmA;   // nb*nb leaf norms of A
-    const double *nrmB;   // nb*nb leaf norms of B
-    const double *rootA;  // device scalar: root squared norm of A
-    const double *rootB;  // device scalar: root squared norm of B
-    double tau;
-    int32_t *cnt;         // nb*nb: |R_ij|
-    int32_t *kidx;        // nb*nb*nb: R_ij at kidx[(i*nb+j)*nb ...], increasing k
-};
-
-// Dispatch order of output tiles for the leaf products: the tiles in Morton
-// (Z) order, so that a contiguous range of ranks is a compact 2-D block of C.
+// Dispatch order of output tiles: Morton (Z) order of the nb x nb tile grid.
 void tile_order(int nb, int32_t *order /* nb*nb */);
 
-// Leaf products of one C = A (x)_tau B over the culled lists.
-struct GemmProb {
-    const void *A;
-    const void *B;
-    void *C;
-    const int32_t *cnt;
-    const int32_t *kidx;
-    double *qC;    // leaf level (P x P) of C's squared-norm pyramid
-    double *part;  // MODE_NSX: per tile (sum (I-x)^2, trace x) over the logical block
+// ---------------------------------------------------------------------------
+// Newton-Schulz solve state, one per solve, in device memory.  Kernels read
+// the current iterate's buffer parity and the running flag from here, so a
+// whole iteration is enqueued without the host deciding anything.
+// ---------------------------------------------------------------------------
+constexpr int ST_RUNNING = 1000;
+
+struct SolveState {
+    int status;       // ST_RUNNING, or the final spamm_status
+    int k;            // index of the current iterate (updates performed so far)
+    int parity;       // y/z buffer holding the current iterate
+    int nondecrease;  // consecutive r_k >= 0.99 r_{k-1}
+    double r0, r_prev, r, t;
+    int64_t triples;  // retained triples of all products so far
+};
+
+struct SolveDesc {
+    SolveState *state;
+    int64_t n;
+    int nb;
+    int maxit, stagnation_stop;
+    double tol;
+    const double *part;  // nb*nb*2: per-tile (sum (I-x)^2, trace x) of the x product
+    const int32_t *cnt_x, *cnt_y, *cnt_z;
+    double *hist_r, *hist_t;
+    int64_t *hist_nR;    // 3 per iteration
+};
+
+// ---------------------------------------------------------------------------
+// One product C = A (x)_tau B as the kernels see it.  Operands that alternate
+// between two buffers are pairs indexed by the solve's parity (a product
+// without a solve uses index 0).  A product with a solve runs only while
+// that solve is running.
+// ---------------------------------------------------------------------------
+struct ProdDesc {
+    int64_t n;
+    int nb, P;
+    double tau;
+    const void *A[2];
+    const void *B[2];
+    void *C[2];
+    const double *nrmA[2], *nrmB[2];    // leaf norms: nb*nb row-major, then the transpose
+    const double *rootA[2], *rootB[2];  // root squared norms
+    double *qC[2];                      // C's squared-norm pyramid (leaf level written by the product)
+    double *nrmC[2];                    // C's leaf norms (written by the pyramid pass)
+    int32_t *cnt;                       // nb*nb retained counts
+    int32_t *kidx;                      // nb*nb*nb retained k lists
+    double *part;                       // non-null: Newton-Schulz x product (writes h and partials)
+    const SolveState *state;            // null: always runs, parity 0
+};
+
+constexpr int NBUCKET = 64;  // longest-first buckets of the large-table work-list sort
+
+// One output tile of one product, with every pointer already resolved for the
+// current parity, so a leaf-product workgroup starts with a single load.
+struct Job {
+    const void *a_row;    // tile (i, 0) of A; tile (i, k) at a_row + k * b*b elements
+    const void *b_col;    // tile (0, j) of B; tile (k, j) at b_col + k * nb*b*b elements
+    void *c;              // tile (i, j) of C
+    double *qc;           // C's leaf squared norm (i, j)
+    double *part;         // Newton-Schulz x product: 2 partial sums of this tile; else null
+    const int32_t *list;  // retained k, increasing
+    int64_t n;            // logical order
+    int nb, cnt, i, j;
+    int k0, k1;           // list[0], list[1] when present (the first stages need no list load)
+};
+
+// Device-side tables of one set of products, built on the host when the set
+// changes and then reused by every launch over that set.
+struct ProdTable {
+    const ProdDesc *prods;    // device array
+    int nprod;
+    const int32_t *cull_pre;  // nprod+1 prefix of cull blocks (ceil(nb*nb/4) per product)
+    const int32_t *tile_pre;  // nprod+1 prefix of nb*nb tiles
+    const int32_t *pyr_pre;   // nprod+1 prefix of first-pass pyramid regions
+    const int32_t *pyr2_pre;  // nprod+1 prefix of second-pass pyramid blocks (1 per product with P > 32)
+    const int32_t *morton;    // concatenated Morton orders, product p's at tile_pre[p]
+    int32_t *work;            // tile_pre[nprod] entries: longest-first global tile ids
+    Job *jobs;                // the same list expanded into job records
+    int32_t *work_count;      // device scalar: valid entries in `work` and `jobs`
+    int32_t *hist;            // NBUCKET * hist_blocks scratch for the large-table sort
+    int hist_blocks;
+    int total_cull, total_tiles, total_pyr, total_pyr2;
+    int max_nb;
 };
 
 // ---- launchers (all asynchronous on `st`; return the launch error) --------
 hipError_t launch_check_input(const double *s, int64_t n, int64_t ld, double *part, double *out3, hipStream_t st);
 hipError_t launch_colsum_max(const double *s, int64_t n, int64_t ld, double mu, double *colsum, double *out1,
                              hipStream_t st);
-hipError_t launch_ingest(int prec, const double *s, int64_t ld, double mu, double c, const Geom &g, Mat m,
-                         hipStream_t st);
-hipError_t launch_identity(int prec, const Geom &g, Mat m, hipStream_t st);
-hipError_t launch_pyramid(const Geom &g, Mat m, hipStream_t st);
-hipError_t launch_pyramid2(const Geom &g, Mat m0, Mat m1, hipStream_t st);
-hipError_t launch_cull(const Geom &g, const CullProb *probs, int nprob, hipStream_t st);
-// Longest-first work list for one leaf-product launch: every (problem, tile)
-// pair, encoded p*nb*nb + t, ordered by decreasing |R_ij| (counting sort in
-// one workgroup).  `morton` gives the base order inside each count bucket.
-hipError_t launch_lpt_order(const Geom &g, const int32_t *cnt0, const int32_t *cnt1, int nprob,
-                            const int32_t *morton, int32_t *work, hipStream_t st);
-hipError_t launch_gemm(int prec, int mode, const Geom &g, const int32_t *work, const GemmProb *probs, int nprob,
-                       hipStream_t st);
-hipError_t launch_ns_reduce(const Geom &g, const double *part, const int32_t *cntX, const int32_t *cntY,
-                            const int32_t *cntZ, int k, double *hist_r, double *hist_t, int64_t *hist_nR,
-                            double *out2, hipStream_t st);
+hipError_t launch_ingest(int prec, const double *s, int64_t ld, double mu, double c, const Geom &g, void *tiles,
+                         double *qleaf, hipStream_t st);
+hipError_t launch_identity(int prec, const Geom &g, void *tiles, double *qleaf, hipStream_t st);
+// Pyramid of one or two operands (squared-norm pyramid q; leaf norms nrm,
+// 2*nb*nb doubles: row-major, then transposed).
+hipError_t launch_pyramid(const Geom &g, double *q0, double *nrm0, double *q1, double *nrm1, int nops,
+                          hipStream_t st);
 hipError_t launch_egress(int prec, const Geom &g, const void *tiles, double *out, int64_t ld, double scale,
                          int divide, hipStream_t st);
 hipError_t launch_norms_out(const Geom &g, const double *q, double *out, hipStream_t st);
@@ -88,5 +134,18 @@ hipError_t launch_count_triples(const Geom &g, const int32_t *cnt, int64_t *offs
                                 hipStream_t st);
 hipError_t launch_write_triples(const Geom &g, const int32_t *cnt, const int32_t *kidx, const int64_t *offs,
                                 int32_t *triples, hipStream_t st);
+
+// Batched stages over a product table.
+hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st);
+// Longest-first job list for leaf tiles of size `leaf` and element size `esz` bytes.
+hipError_t launch_plan_tab(const ProdTable &t, int leaf, int esz, hipStream_t st);
+hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t st);
+hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st);  // pyramid of each product's C
+// Per solve: r_k, t_k, |R| records and the stop decision.
+hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, hipStream_t st);
+// After a (y, z) update: parity ^= 1, k += 1 for running solves.
+hipError_t launch_ns_advance(const SolveDesc *solves, int nsolve, hipStream_t st);
+// Copy each solve's state into a contiguous array (for one read-back).
+hipError_t launch_gather_states(const SolveDesc *solves, int nsolve, SolveState *out, hipStream_t st);
 
 }  // namespace spk

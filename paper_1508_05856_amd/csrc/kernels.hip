@@ -242,50 +242,46 @@ __global__ __launch_bounds__(256) void k_identity(Geom g, T *__restrict__ tiles,
     }
 }
 
-hipError_t launch_ingest(int prec, const double *s, int64_t ld, double mu, double c, const Geom &g, Mat m,
-                         hipStream_t st) {
+hipError_t launch_ingest(int prec, const double *s, int64_t ld, double mu, double c, const Geom &g, void *tiles,
+                         double *qleaf, hipStream_t st) {
     const unsigned nt = (unsigned)g.nb * g.nb;
     if (prec == P_F64)
-        hipLaunchKernelGGL(k_ingest<double>, dim3(nt), dim3(256), 0, st, s, ld, mu, c, g, (double *)m.tiles, m.q);
+        hipLaunchKernelGGL(k_ingest<double>, dim3(nt), dim3(256), 0, st, s, ld, mu, c, g, (double *)tiles, qleaf);
     else
-        hipLaunchKernelGGL(k_ingest<float>, dim3(nt), dim3(256), 0, st, s, ld, mu, c, g, (float *)m.tiles, m.q);
+        hipLaunchKernelGGL(k_ingest<float>, dim3(nt), dim3(256), 0, st, s, ld, mu, c, g, (float *)tiles, qleaf);
     return hipGetLastError();
 }
 
-hipError_t launch_identity(int prec, const Geom &g, Mat m, hipStream_t st) {
+hipError_t launch_identity(int prec, const Geom &g, void *tiles, double *qleaf, hipStream_t st) {
     const unsigned nt = (unsigned)g.nb * g.nb;
     if (prec == P_F64)
-        hipLaunchKernelGGL(k_identity<double>, dim3(nt), dim3(256), 0, st, g, (double *)m.tiles, m.q);
+        hipLaunchKernelGGL(k_identity<double>, dim3(nt), dim3(256), 0, st, g, (double *)tiles, qleaf);
     else
-        hipLaunchKernelGGL(k_identity<float>, dim3(nt), dim3(256), 0, st, g, (float *)m.tiles, m.q);
+        hipLaunchKernelGGL(k_identity<float>, dim3(nt), dim3(256), 0, st, g, (float *)tiles, qleaf);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Norm pyramid: each block reduces an R x R region (R = min(S, 32)) of the
-// level of side S through up to five parent levels, each parent's squared
-// norm being (q00 + q01) + (q10 + q11).  With nrm != nullptr the launch is on
-// the leaf level and also writes the leaf norms of the real blocks.
-// blockIdx.y selects one of two operands.
+// Norm pyramid: a block reduces an R x R region (R = min(S, 32)) of the level
+// of side S through up to five parent levels, each parent's squared norm
+// being (q00 + q01) + (q10 + q11).  On the leaf level (leaf != 0) it also
+// writes the leaf norms sqrt(q) of the real blocks, which the cull reads.
 // ---------------------------------------------------------------------------
-struct PyrArgs {
-    double *q;
-    double *nrm;
-};
-
-__global__ __launch_bounds__(256) void k_pyramid(PyrArgs a0, PyrArgs a1, int P, int S, int nb, int leaf) {
-    __shared__ double buf[32 * 32];
-    const PyrArgs a = blockIdx.y == 0 ? a0 : a1;
+__device__ void pyramid_region(double *q, double *nrm, int P, int S, int nb, int leaf, int region, double *buf) {
     const int R = S < 32 ? S : 32;
     const int G = S / R;  // regions per side
-    const int gy = blockIdx.x / G, gx = blockIdx.x % G;
-    const double *lvl = a.q + dev_level_off(P, S);
+    const int gy = region / G, gx = region % G;
+    const double *lvl = q + dev_level_off(P, S);
     for (int e = threadIdx.x; e < R * R; e += 256) {
         const int r = e / R, c = e % R;
         const int64_t gr = (int64_t)gy * R + r, gc = (int64_t)gx * R + c;
         const double v = lvl[gr * S + gc];
         buf[e] = v;
-        if (leaf && gr < nb && gc < nb) a.nrm[gr * nb + gc] = sqrt(v);
+        if (leaf && gr < nb && gc < nb) {
+            const double nv = sqrt(v);
+            nrm[gr * nb + gc] = nv;                          // (i, k) row-major
+            nrm[(int64_t)nb * nb + gc * nb + gr] = nv;       // transposed copy for B-side reads
+        }
     }
     __syncthreads();
     int s = R;
@@ -306,7 +302,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a0, PyrArgs a1, int P, 
             buf[e] = v;
             const int pr = e / h, pc = e % h;
             const int64_t gr = (int64_t)gy * h + pr, gc = (int64_t)gx * h + pc;
-            a.q[dev_level_off(P, Spar) + gr * Spar + gc] = v;
+            q[dev_level_off(P, Spar) + gr * Spar + gc] = v;
         }
         __syncthreads();
         s = h;
@@ -314,14 +310,23 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a0, PyrArgs a1, int P, 
     }
 }
 
-static hipError_t pyramid_impl(const Geom &g, Mat m0, Mat m1, int nprob, hipStream_t st) {
-    PyrArgs a0{m0.q, m0.nrm}, a1{m1.q, m1.nrm};
+__global__ __launch_bounds__(256) void k_pyramid(double *q0, double *nrm0, double *q1, double *nrm1, int P, int S,
+                                                 int nb, int leaf) {
+    __shared__ double buf[32 * 32];
+    if (blockIdx.y == 0)
+        pyramid_region(q0, nrm0, P, S, nb, leaf, blockIdx.x, buf);
+    else
+        pyramid_region(q1, nrm1, P, S, nb, leaf, blockIdx.x, buf);
+}
+
+hipError_t launch_pyramid(const Geom &g, double *q0, double *nrm0, double *q1, double *nrm1, int nops,
+                          hipStream_t st) {
     int S = g.P;
     int leaf = 1;
     while (true) {
         const int R = S < 32 ? S : 32;
         const int G = S / R;
-        hipLaunchKernelGGL(k_pyramid, dim3(G * G, nprob), dim3(256), 0, st, a0, a1, g.P, S, g.nb, leaf);
+        hipLaunchKernelGGL(k_pyramid, dim3(G * G, nops), dim3(256), 0, st, q0, nrm0, q1, nrm1, g.P, S, g.nb, leaf);
         leaf = 0;
         if (G == 1) break;
         S = G;
@@ -329,9 +334,54 @@ static hipError_t pyramid_impl(const Geom &g, Mat m0, Mat m1, int nprob, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_pyramid(const Geom &g, Mat m, hipStream_t st) { return pyramid_impl(g, m, m, 1, st); }
-hipError_t launch_pyramid2(const Geom &g, Mat m0, Mat m1, hipStream_t st) {
-    return pyramid_impl(g, m0, m1, 2, st);
+// ---------------------------------------------------------------------------
+// Product tables.  Every batched launch covers all products of a table; a
+// block finds its product by binary search in a prefix array and returns at
+// once when the product's solve is not running.
+// ---------------------------------------------------------------------------
+__device__ inline int find_slot(const int32_t *pre, int n, int x) {
+    // largest p in [0, n) with pre[p] <= x  (pre[0] = 0 <= x < pre[n])
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline bool prod_running(const ProdDesc &d) { return d.state == nullptr || d.state->status == ST_RUNNING; }
+__device__ inline int prod_parity(const ProdDesc &d) { return d.state ? d.state->parity : 0; }
+
+// Pyramid of each running product's C: pass 1 on the leaf level, pass 2 (one
+// block per product with P > 32) from level P/32 to the root.
+__global__ __launch_bounds__(256) void k_pyramid_tab1(const ProdDesc *__restrict__ prods,
+                                                      const int32_t *__restrict__ pre, int nprod) {
+    __shared__ double buf[32 * 32];
+    const int p = find_slot(pre, nprod, blockIdx.x);
+    const ProdDesc &d = prods[p];
+    if (!prod_running(d)) return;
+    const int par = prod_parity(d);
+    pyramid_region(d.qC[par], d.nrmC[par], d.P, d.P, d.nb, 1, blockIdx.x - pre[p], buf);
+}
+
+__global__ __launch_bounds__(256) void k_pyramid_tab2(const ProdDesc *__restrict__ prods,
+                                                      const int32_t *__restrict__ pre, int nprod) {
+    __shared__ double buf[32 * 32];
+    const int p = find_slot(pre, nprod, blockIdx.x);
+    const ProdDesc &d = prods[p];
+    if (!prod_running(d)) return;
+    const int par = prod_parity(d);
+    pyramid_region(d.qC[par], d.nrmC[par], d.P, d.P / 32, d.nb, 0, 0, buf);
+}
+
+hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st) {
+    hipLaunchKernelGGL(k_pyramid_tab1, dim3(t.total_pyr), dim3(256), 0, st, t.prods, t.pyr_pre, t.nprod);
+    if (t.total_pyr2 > 0)
+        hipLaunchKernelGGL(k_pyramid_tab2, dim3(t.total_pyr2), dim3(256), 0, st, t.prods, t.pyr2_pre, t.nprod);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -339,43 +389,245 @@ hipError_t launch_pyramid2(const Geom &g, Mat m0, Mat m1, hipStream_t st) {
 // thr = tau * (||A|| * ||B||), in increasing k.  Flat enumeration: since a
 // parent's squared norm is a sum of non-negative children, every ancestor
 // triple of a kept leaf triple is kept, so this equals the recursive set.
+// One wave per output tile: lane l tests k = kb + l, a ballot gives the kept
+// k of the group of 64 and each kept lane writes its k at its rank.  A row of
+// A's leaf norms and a column of B's (from the transposed copy) are read
+// coalesced.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_cull(CullProb p0, CullProb p1, int nb) {
-    const CullProb p = blockIdx.z == 0 ? p0 : p1;
-    const int i = blockIdx.y;
-    const int j = blockIdx.x * 64 + threadIdx.x;
-    if (j >= nb) return;
-    const double thr = p.tau * (sqrt(*p.rootA) * sqrt(*p.rootB));
-    const double *na = p.nrmA + (int64_t)i * nb;
-    const double *nbj = p.nrmB + j;
-    int32_t *out = p.kidx + ((int64_t)i * nb + j) * nb;
-    int c = 0;
-    for (int k = 0; k < nb; ++k) {
-        const double prod = na[k] * nbj[(int64_t)k * nb];
-        if (!(prod < thr)) out[c++] = k;
+__global__ __launch_bounds__(256) void k_cull_tab(const ProdDesc *__restrict__ prods,
+                                                  const int32_t *__restrict__ pre, int nprod) {
+    const int p = find_slot(pre, nprod, blockIdx.x);
+    const ProdDesc &d = prods[p];
+    if (!prod_running(d)) return;
+    const int par = prod_parity(d);
+    const int nb = d.nb;
+    const int t = (blockIdx.x - pre[p]) * 4 + (threadIdx.x >> 6);
+    if (t >= nb * nb) return;
+    const int lane = threadIdx.x & 63;
+    const int i = t / nb, j = t % nb;
+    const double thr = d.tau * (sqrt(*d.rootA[par]) * sqrt(*d.rootB[par]));
+    const double *na = d.nrmA[par] + (int64_t)i * nb;
+    const double *nbt = d.nrmB[par] + (int64_t)nb * nb + (int64_t)j * nb;  // ||B_kj|| at nbt[k]
+    int32_t *out = d.kidx + (int64_t)t * nb;
+    int base = 0;
+    for (int kb = 0; kb < nb; kb += 64) {
+        const int k = kb + lane;
+        bool keep = false;
+        if (k < nb) {
+            const double prod = na[k] * nbt[k];
+            keep = !(prod < thr);
+        }
+        const unsigned long long mask = __ballot(keep);
+        if (keep) out[base + __popcll(mask & ((1ull << lane) - 1ull))] = k;
+        base += __popcll(mask);
     }
-    p.cnt[(int64_t)i * nb + j] = c;
+    if (lane == 0) d.cnt[t] = base;
 }
 
-hipError_t launch_cull(const Geom &g, const CullProb *probs, int nprob, hipStream_t st) {
-    const CullProb p1 = nprob > 1 ? probs[1] : probs[0];
-    hipLaunchKernelGGL(k_cull, dim3((g.nb + 63) / 64, g.nb, nprob), dim3(64), 0, st, probs[0], p1, g.nb);
+hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st) {
+    hipLaunchKernelGGL(k_cull_tab, dim3(t.total_cull), dim3(256), 0, st, t.prods, t.cull_pre, t.nprod);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Leaf products on MFMA.  One workgroup per output tile (i,j); 64x64 tiles
-// use four waves, each owning a 32x32 quadrant (2x2 blocks of 16x16); 32x32
-// and 16x16 tiles use one wave.  For every retained k in increasing order the
-// A_ik and B_kj tiles are staged through LDS (rows padded by 16 bytes), the
-// next pair being fetched into registers while the current one is consumed.
+// Longest-first work list: the tiles of all running products, ordered by
+// decreasing retained count, so the heaviest tiles are dispatched first and
+// a launch ends on short tiles.  Order inside a count bucket is whatever the
+// atomics give; no product depends on it.  Entries are global tile ids
+// tile_pre[p] + (i*nb + j); the base order is Morton within each product.
+// Small tables: one workgroup, one bucket per count.  Large tables: NBUCKET
+// coarse buckets (count capped), per-workgroup histograms, a scan, a scatter.
+// ---------------------------------------------------------------------------
+__device__ inline int item_count(const ProdDesc *prods, const int32_t *tile_pre, const int32_t *morton, int nprod,
+                                 int g, int &p, int &t) {
+    p = find_slot(tile_pre, nprod, g);
+    const ProdDesc &d = prods[p];
+    if (!prod_running(d)) return -1;
+    t = morton[g];
+    return d.cnt[t];
+}
+
+// Job record of tile t of product p for element size esz (pointers resolved
+// for the product's current parity).
+__device__ inline Job make_job(const ProdDesc &d, int t, int cnt, int b, int esz) {
+    const int par = prod_parity(d);
+    const int nb = d.nb, i = t / nb, j = t % nb;
+    const int64_t ts = (int64_t)b * b * esz;
+    Job J;
+    J.a_row = (const char *)d.A[par] + (int64_t)i * nb * ts;
+    J.b_col = (const char *)d.B[par] + (int64_t)j * ts;
+    J.c = (char *)d.C[par] + (int64_t)t * ts;
+    J.qc = d.qC[par] + (int64_t)i * d.P + j;
+    J.part = d.part ? d.part + 2 * (int64_t)t : nullptr;
+    J.list = d.kidx + (int64_t)t * nb;
+    J.n = d.n;
+    J.nb = nb;
+    J.cnt = cnt;
+    J.i = i;
+    J.j = j;
+    J.k0 = cnt > 0 ? J.list[0] : 0;
+    J.k1 = cnt > 1 ? J.list[1] : 0;
+    return J;
+}
+
+__global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict__ prods,
+                                                     const int32_t *__restrict__ tile_pre,
+                                                     const int32_t *__restrict__ morton, int nprod, int max_nb,
+                                                     int32_t *__restrict__ work, int32_t *__restrict__ work_count) {
+    extern __shared__ int hist[];  // max_nb + 1 bins
+    const int total = tile_pre[nprod];
+    for (int c = threadIdx.x; c <= max_nb; c += 1024) hist[c] = 0;
+    __syncthreads();
+    for (int g = threadIdx.x; g < total; g += 1024) {
+        int p, t;
+        const int c = item_count(prods, tile_pre, morton, nprod, g, p, t);
+        if (c >= 0) atomicAdd(&hist[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int c = max_nb; c >= 0; --c) {
+            const int h = hist[c];
+            hist[c] = run;
+            run += h;
+        }
+        *work_count = run;
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < total; g += 1024) {
+        int p, t;
+        const int c = item_count(prods, tile_pre, morton, nprod, g, p, t);
+        if (c >= 0) work[atomicAdd(&hist[c], 1)] = tile_pre[p] + t;
+    }
+}
+
+__device__ inline int bucket_of(int c) { return c < NBUCKET - 1 ? c : NBUCKET - 1; }
+
+__global__ __launch_bounds__(256) void k_plan_hist(const ProdDesc *__restrict__ prods,
+                                                   const int32_t *__restrict__ tile_pre,
+                                                   const int32_t *__restrict__ morton, int nprod, int nblk,
+                                                   int32_t *__restrict__ hist) {
+    __shared__ int h[NBUCKET];
+    const int total = tile_pre[nprod];
+    const int chunk = (total + nblk - 1) / nblk;
+    const int lo = blockIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
+    for (int b = threadIdx.x; b < NBUCKET; b += 256) h[b] = 0;
+    __syncthreads();
+    for (int g = lo + threadIdx.x; g < hi; g += 256) {
+        int p, t;
+        const int c = item_count(prods, tile_pre, morton, nprod, g, p, t);
+        if (c >= 0) atomicAdd(&h[bucket_of(c)], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < NBUCKET; b += 256) hist[b * nblk + blockIdx.x] = h[b];
+}
+
+// Exclusive scan of hist in the order (bucket descending, block ascending).
+__global__ __launch_bounds__(1024) void k_plan_scan(int32_t *__restrict__ hist, int nblk,
+                                                    int32_t *__restrict__ work_count) {
+    __shared__ int part[1024];
+    const int m = NBUCKET * nblk;
+    const int per = (m + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = lo + per < m ? lo + per : m;
+    auto at = [&](int L) -> int32_t & {  // L-th entry in scan order
+        const int b = NBUCKET - 1 - L / nblk, w = L % nblk;
+        return hist[b * nblk + w];
+    };
+    int s = 0;
+    for (int L = lo; L < hi; ++L) s += at(L);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int x = 0; x < 1024; ++x) {
+            const int v = part[x];
+            part[x] = run;
+            run += v;
+        }
+        *work_count = run;
+    }
+    __syncthreads();
+    int run = part[threadIdx.x];
+    for (int L = lo; L < hi; ++L) {
+        const int v = at(L);
+        at(L) = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_plan_scatter(const ProdDesc *__restrict__ prods,
+                                                      const int32_t *__restrict__ tile_pre,
+                                                      const int32_t *__restrict__ morton, int nprod, int nblk,
+                                                      const int32_t *__restrict__ hist, int32_t *__restrict__ work) {
+    __shared__ int cur[NBUCKET];
+    const int total = tile_pre[nprod];
+    const int chunk = (total + nblk - 1) / nblk;
+    const int lo = blockIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
+    for (int q = threadIdx.x; q < NBUCKET; q += 256) cur[q] = hist[q * nblk + blockIdx.x];
+    __syncthreads();
+    for (int g = lo + threadIdx.x; g < hi; g += 256) {
+        int p, t;
+        const int c = item_count(prods, tile_pre, morton, nprod, g, p, t);
+        if (c >= 0) work[atomicAdd(&cur[bucket_of(c)], 1)] = tile_pre[p] + t;
+    }
+}
+
+// Expands the sorted tile ids into job records, one thread per entry.
+__global__ __launch_bounds__(256) void k_make_jobs(const ProdDesc *__restrict__ prods,
+                                                   const int32_t *__restrict__ tile_pre, int nprod,
+                                                   const int32_t *__restrict__ work,
+                                                   const int32_t *__restrict__ work_count, int b, int esz,
+                                                   Job *__restrict__ jobs) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= *work_count) return;
+    const int gid = work[idx];
+    const int p = find_slot(tile_pre, nprod, gid);
+    const int t = gid - tile_pre[p];
+    const ProdDesc &d = prods[p];
+    jobs[idx] = make_job(d, t, d.cnt[t], b, esz);
+}
+
+hipError_t launch_plan_tab(const ProdTable &t, int leaf, int esz, hipStream_t st) {
+    if (t.hist_blocks == 0) {
+        hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), (t.max_nb + 1) * sizeof(int), st, t.prods, t.tile_pre,
+                           t.morton, t.nprod, t.max_nb, t.work, t.work_count);
+    } else {
+        hipLaunchKernelGGL(k_plan_hist, dim3(t.hist_blocks), dim3(256), 0, st, t.prods, t.tile_pre, t.morton,
+                           t.nprod, t.hist_blocks, t.hist);
+        hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, t.hist, t.hist_blocks, t.work_count);
+        hipLaunchKernelGGL(k_plan_scatter, dim3(t.hist_blocks), dim3(256), 0, st, t.prods, t.tile_pre, t.morton,
+                           t.nprod, t.hist_blocks, t.hist, t.work);
+    }
+    hipLaunchKernelGGL(k_make_jobs, dim3((t.total_tiles + 255) / 256), dim3(256), 0, st, t.prods, t.tile_pre,
+                       t.nprod, t.work, t.work_count, leaf, esz, t.jobs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Leaf products on MFMA.  One workgroup per output tile, taken from the
+// longest-first work list; 64x64 tiles use four waves, each owning a 32x32
+// quadrant (2x2 blocks of 16x16), 32x32 and 16x16 tiles one wave.  The
+// retained k of the tile are consumed in increasing order, in pipeline
+// stages (half a tile of k for 64x64 tiles): each stage of A_ik and B_kj goes
+// global -> registers -> one of two LDS buffers, two stages ahead of the
+// MFMAs that use it.
 // Epilogue: the C tile and its squared norm (of the stored values, FP64);
-// in MODE_NSX the tile written is h = 1.5 I_n - 0.5 x and the FP64 partial
-// sums of (I_n - x)^2 and of the trace over the logical block.
+// for a Newton-Schulz x product the tile written is h = 1.5 I_n - 0.5 x, with
+// the FP64 partial sums of (I_n - x)^2 and of the trace over the logical block.
 // ---------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+
+// Pointers read from job records are generic; marking them global lets the
+// compiler use global (not flat) loads and stores, whose completion is
+// tracked apart from LDS traffic.
+template <typename T>
+using gptr = T __attribute__((address_space(1))) *;
+template <typename T>
+__device__ inline gptr<T> to_global(T *p) {
+    return (gptr<T>)p;
+}
 
 template <typename T>
 struct Mfma;
@@ -423,9 +675,9 @@ struct TileCfg {
     static constexpr int B_CH = KS * B / VEC / NT;
 };
 
-template <typename T, int B, int MODE>
-__global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0, GemmProb p1, Geom g,
-                                                                    const int32_t *__restrict__ order) {
+template <typename T, int B>
+__global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(const Job *__restrict__ jobs,
+                                                                    const int32_t *__restrict__ work_count) {
     using C = TileCfg<T, B>;
     using M = Mfma<T>;
     typedef typename M::acc_t acc_t;
@@ -435,19 +687,20 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
     __shared__ __attribute__((aligned(16))) T Bs[2][C::KS * C::LDB];
     __shared__ double red[3 * C::WAVES];
 
-    const int nb = g.nb;
-    const int w_item = order[blockIdx.x];
-    const int T_tiles = nb * nb;
-    const bool second = w_item >= T_tiles;
-    const GemmProb p = second ? p1 : p0;
-    const int t = second ? w_item - T_tiles : w_item;
-    const int i = t / nb, j = t % nb;
+    // both loads are issued before the test (the job array always has a
+    // record for every block of the grid)
+    const int nwork = *work_count;
+    const Job J = jobs[blockIdx.x];
+    if ((int)blockIdx.x >= nwork) return;
+    const bool nsx = J.part != nullptr;
+    const int nb = J.nb;
+    const int i = J.i, j = J.j;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = (C::WAVES == 4) ? (w >> 1) : 0, wc = (C::WAVES == 4) ? (w & 1) : 0;
-    const int cnt = p.cnt[t];
-    const int32_t *list = p.kidx + (int64_t)t * nb;
-    const T *Ab = (const T *)p.A;
-    const T *Bb = (const T *)p.B;
+    const int cnt = J.cnt;
+    const gptr<const int32_t> list = to_global(J.list);
+    const gptr<const T> Arow = to_global((const T *)J.a_row);
+    const gptr<const T> Bcol = to_global((const T *)J.b_col);
     constexpr int64_t TS = (int64_t)B * B;
     const int S = cnt * C::SPT;  // pipeline stages
 
@@ -461,14 +714,15 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
 
     // stage s covers k-columns [ks*KS, ks*KS+KS) of triple (i, j, list[s/SPT])
     auto gload = [&](int s, vec_t *ra, vec_t *rb) {
-        const int k = list[s / C::SPT];
+        const int e = s / C::SPT;
+        const int k = e == 0 ? J.k0 : (e == 1 ? J.k1 : list[e]);
         const int ks = s % C::SPT;
-        const T *a = Ab + ((int64_t)i * nb + k) * TS + ks * C::KS;
-        const vec_t *b = (const vec_t *)(Bb + ((int64_t)k * nb + j) * TS + (int64_t)ks * C::KS * B);
+        const gptr<const T> a = Arow + (int64_t)k * TS + ks * C::KS;
+        const gptr<const vec_t> b = (gptr<const vec_t>)(Bcol + (int64_t)k * nb * TS + (int64_t)ks * C::KS * B);
 #pragma unroll
         for (int c = 0; c < C::A_CH; ++c) {
             const int el = (tid + c * C::NT) * C::VEC;
-            ra[c] = *(const vec_t *)(a + (el / C::KS) * B + el % C::KS);
+            ra[c] = *(gptr<const vec_t>)(a + (el / C::KS) * B + el % C::KS);
         }
 #pragma unroll
         for (int c = 0; c < C::B_CH; ++c) rb[c] = b[tid + c * C::NT];
@@ -528,7 +782,7 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
     }
 
     // epilogue
-    T *Ct = (T *)p.C + (int64_t)t * TS;
+    const gptr<T> Ct = to_global((T *)J.c);
     double qs = 0.0, r2 = 0.0, tr = 0.0;
 #pragma unroll
     for (int bi = 0; bi < C::NBLK; ++bi)
@@ -540,10 +794,10 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
                 const int col = wc * C::Q + bj * 16 + (lane & 15);
                 const double x = (double)acc[bi][bj][r];
                 T out;
-                if (MODE == MODE_NSX) {
+                if (nsx) {
                     const int64_t gi = (int64_t)i * B + row, gj = (int64_t)j * B + col;
-                    const bool diag = (gi == gj) && (gi < g.n);
-                    const bool logical = (gi < g.n) && (gj < g.n);
+                    const bool diag = (gi == gj) && (gi < J.n);
+                    const bool logical = (gi < J.n) && (gj < J.n);
                     const double h = (diag ? 1.5 : 0.0) - 0.5 * x;
                     const double ex = (diag ? 1.0 : 0.0) - x;
                     if (logical) r2 += ex * ex;
@@ -557,7 +811,7 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
                 qs += dv * dv;
             }
     qs = wave_sum(qs);
-    if (MODE == MODE_NSX) {
+    if (nsx) {
         r2 = wave_sum(r2);
         tr = wave_sum(tr);
     }
@@ -574,111 +828,60 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(GemmProb p0,
             b += red[C::WAVES + x];
             c += red[2 * C::WAVES + x];
         }
-        p.qC[(int64_t)i * g.P + j] = a;
-        if (MODE == MODE_NSX) {
-            p.part[2 * (int64_t)t] = b;
-            p.part[2 * (int64_t)t + 1] = c;
+        *to_global(J.qc) = a;
+        if (nsx) {
+            to_global(J.part)[0] = b;
+            to_global(J.part)[1] = c;
         }
     }
 }
 
 template <typename T, int B>
-static void gemm_dispatch_mode(int mode, const Geom &g, const int32_t *order, const GemmProb &a, const GemmProb &b,
-                               int nprob, hipStream_t st) {
-    dim3 grid((unsigned)g.nb * g.nb * nprob);
-    dim3 block(TileCfg<T, B>::NT);
-    if (mode == MODE_NSX)
-        hipLaunchKernelGGL((k_leaf_gemm<T, B, MODE_NSX>), grid, block, 0, st, a, b, g, order);
-    else
-        hipLaunchKernelGGL((k_leaf_gemm<T, B, MODE_PLAIN>), grid, block, 0, st, a, b, g, order);
+static void gemm_launch(const ProdTable &t, hipStream_t st) {
+    hipLaunchKernelGGL((k_leaf_gemm<T, B>), dim3(t.total_tiles), dim3(TileCfg<T, B>::NT), 0, st, t.jobs,
+                       t.work_count);
 }
 
 template <typename T>
-static void gemm_dispatch_b(int mode, const Geom &g, const int32_t *order, const GemmProb &a, const GemmProb &b,
-                            int nprob, hipStream_t st) {
-    if (g.b == 64)
-        gemm_dispatch_mode<T, 64>(mode, g, order, a, b, nprob, st);
-    else if (g.b == 32)
-        gemm_dispatch_mode<T, 32>(mode, g, order, a, b, nprob, st);
+static void gemm_dispatch_b(int leaf, const ProdTable &t, hipStream_t st) {
+    if (leaf == 64)
+        gemm_launch<T, 64>(t, st);
+    else if (leaf == 32)
+        gemm_launch<T, 32>(t, st);
     else
-        gemm_dispatch_mode<T, 16>(mode, g, order, a, b, nprob, st);
+        gemm_launch<T, 16>(t, st);
 }
 
-hipError_t launch_gemm(int prec, int mode, const Geom &g, const int32_t *order, const GemmProb *probs, int nprob,
-                       hipStream_t st) {
-    const GemmProb p1 = nprob > 1 ? probs[1] : probs[0];
+hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t st) {
     if (prec == P_F64)
-        gemm_dispatch_b<double>(mode, g, order, probs[0], p1, nprob, st);
+        gemm_dispatch_b<double>(leaf, t, st);
     else
-        gemm_dispatch_b<float>(mode, g, order, probs[0], p1, nprob, st);
+        gemm_dispatch_b<float>(leaf, t, st);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Longest-first dispatch: counting sort of the (problem, tile) work items by
-// decreasing retained count.  Workgroups are handed out in launch order, so
-// the heaviest tiles start first and the tail of the launch is short tiles.
-// The order inside a bucket is whatever the atomics give; the products do
-// not depend on it.
+// Newton-Schulz control, one workgroup per solve: r_k = sqrt(sum of per-tile
+// (I-x)^2), t_k = (n - trace)/n and the retained-triple counts, summed in a
+// fixed order, then the stop tests in the order: r_k < tol (OK); r_k not
+// finite or > 10 max(r_0, sqrt(n)) (diverged); two consecutive
+// r_k >= 0.99 r_{k-1} (stagnated, opt-in); k == maxit (not converged).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_lpt_order(const int32_t *__restrict__ cnt0,
-                                                     const int32_t *__restrict__ cnt1, int nprob, int nb,
-                                                     const int32_t *__restrict__ morton, int32_t *__restrict__ work) {
-    extern __shared__ int lds_hist[];  // nb + 1 bins
-    const int T = nb * nb;
-    const int items = nprob * T;
-    for (int c = threadIdx.x; c <= nb; c += 1024) lds_hist[c] = 0;
-    __syncthreads();
-    for (int e = threadIdx.x; e < items; e += 1024) {
-        const int p = e / T, t = morton[e % T];
-        const int c = (p == 0 ? cnt0 : cnt1)[t];
-        atomicAdd(&lds_hist[c], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int c = nb; c >= 0; --c) {
-            const int h = lds_hist[c];
-            lds_hist[c] = run;
-            run += h;
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < items; e += 1024) {
-        const int p = e / T, t = morton[e % T];
-        const int c = (p == 0 ? cnt0 : cnt1)[t];
-        const int pos = atomicAdd(&lds_hist[c], 1);
-        work[pos] = p * T + t;
-    }
-}
-
-hipError_t launch_lpt_order(const Geom &g, const int32_t *cnt0, const int32_t *cnt1, int nprob,
-                            const int32_t *morton, int32_t *work, hipStream_t st) {
-    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), (g.nb + 1) * sizeof(int), st, cnt0,
-                       nprob > 1 ? cnt1 : cnt0, nprob, g.nb, morton, work);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Newton-Schulz reduction: r_k = sqrt(sum of per-tile (I-x)^2), t_k =
-// (n - trace)/n, and |R| of x_k (and of the update that produced y_k, z_k),
-// all summed in a fixed order.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_ns_reduce(const double *__restrict__ part, int64_t ntiles,
-                                                     const int32_t *__restrict__ cntX,
-                                                     const int32_t *__restrict__ cntY,
-                                                     const int32_t *__restrict__ cntZ, int64_t n, int k,
-                                                     double *hist_r, double *hist_t, int64_t *hist_nR,
-                                                     double *out2) {
+__global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict__ solves) {
     __shared__ double sh[16];
+    const SolveDesc &sd = solves[blockIdx.x];
+    SolveState *st = sd.state;
+    if (st->status != ST_RUNNING) return;
+    const int k = st->k;
+    const int64_t ntiles = (int64_t)sd.nb * sd.nb;
     double r2 = 0.0, tr = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
     for (int64_t e = threadIdx.x; e < ntiles; e += 1024) {
-        r2 += part[2 * e];
-        tr += part[2 * e + 1];
-        cx += (double)cntX[e];
+        r2 += sd.part[2 * e];
+        tr += sd.part[2 * e + 1];
+        cx += (double)sd.cnt_x[e];
         if (k > 0) {
-            cy += (double)cntY[e];
-            cz += (double)cntZ[e];
+            cy += (double)sd.cnt_y[e];
+            cz += (double)sd.cnt_z[e];
         }
     }
     r2 = block_sum<1024>(r2, sh);
@@ -686,26 +889,65 @@ __global__ __launch_bounds__(1024) void k_ns_reduce(const double *__restrict__ p
     cx = block_sum<1024>(cx, sh);
     cy = block_sum<1024>(cy, sh);
     cz = block_sum<1024>(cz, sh);
-    if (threadIdx.x == 0) {
-        const double r = sqrt(r2);
-        const double tk = ((double)n - tr) / (double)n;
-        hist_r[k] = r;
-        hist_t[k] = tk;
-        hist_nR[3 * k] = (int64_t)cx;
-        if (k > 0) {
-            hist_nR[3 * (k - 1) + 1] = (int64_t)cy;
-            hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
-        }
-        out2[0] = r;
-        out2[1] = tk;
+    if (threadIdx.x != 0) return;
+    const double r = sqrt(r2);
+    const double tk = ((double)sd.n - tr) / (double)sd.n;
+    sd.hist_r[k] = r;
+    sd.hist_t[k] = tk;
+    sd.hist_nR[3 * k] = (int64_t)cx;
+    if (k > 0) {
+        sd.hist_nR[3 * (k - 1) + 1] = (int64_t)cy;
+        sd.hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
     }
+    st->triples += (int64_t)cx + (int64_t)cy + (int64_t)cz;
+    st->r = r;
+    st->t = tk;
+    if (k == 0) st->r0 = r;
+    int status = ST_RUNNING;
+    if (r < sd.tol) {
+        status = 0;  // SPAMM_OK
+    } else if (!isfinite(r) || r > 10.0 * fmax(st->r0, sqrt((double)sd.n))) {
+        status = -3;  // SPAMM_EDIVERGED
+    } else {
+        if (sd.stagnation_stop && k > 0) {
+            st->nondecrease = (r >= 0.99 * st->r_prev) ? st->nondecrease + 1 : 0;
+            if (st->nondecrease >= 2) status = 2;  // SPAMM_STAGNATED
+        }
+        if (status == ST_RUNNING) {
+            st->r_prev = r;
+            if (k == sd.maxit) status = 1;  // SPAMM_NOT_CONVERGED
+        }
+    }
+    st->status = status;
 }
 
-hipError_t launch_ns_reduce(const Geom &g, const double *part, const int32_t *cntX, const int32_t *cntY,
-                            const int32_t *cntZ, int k, double *hist_r, double *hist_t, int64_t *hist_nR,
-                            double *out2, hipStream_t st) {
-    hipLaunchKernelGGL(k_ns_reduce, dim3(1), dim3(1024), 0, st, part, (int64_t)g.nb * g.nb, cntX, cntY, cntZ,
-                       g.n, k, hist_r, hist_t, hist_nR, out2);
+__global__ __launch_bounds__(64) void k_ns_advance(const SolveDesc *__restrict__ solves, int nsolve) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= nsolve) return;
+    SolveState *st = solves[i].state;
+    if (st->status != ST_RUNNING) return;
+    st->parity ^= 1;
+    st->k += 1;
+}
+
+__global__ __launch_bounds__(64) void k_gather_states(const SolveDesc *__restrict__ solves, int nsolve,
+                                                      SolveState *__restrict__ out) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < nsolve) out[i] = *solves[i].state;
+}
+
+hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, hipStream_t st) {
+    hipLaunchKernelGGL(k_ns_decide, dim3(nsolve), dim3(1024), 0, st, solves);
+    return hipGetLastError();
+}
+
+hipError_t launch_ns_advance(const SolveDesc *solves, int nsolve, hipStream_t st) {
+    hipLaunchKernelGGL(k_ns_advance, dim3((nsolve + 63) / 64), dim3(64), 0, st, solves, nsolve);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_states(const SolveDesc *solves, int nsolve, SolveState *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_states, dim3((nsolve + 63) / 64), dim3(64), 0, st, solves, nsolve, out);
     return hipGetLastError();
 }
 

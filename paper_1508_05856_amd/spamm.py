@@ -26,8 +26,9 @@ STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", STAGNATED: "STAGNATED"
 
 # Every symbol include/spamm.h declares.
 EXPORTS = ("spamm_create", "spamm_destroy", "spamm_last_error", "spamm_pyramid_len", "spamm_norms",
-           "spamm_multiply", "ns_sqrt", "spamm_ns_history", "spamm_profile_enable", "spamm_profile_read",
-           "spamm_profile_reset")
+           "spamm_multiply", "ns_sqrt", "spamm_ns_history", "spamm_solve_footprint", "spamm_solve_begin",
+           "spamm_solve_step", "spamm_solve_poll", "spamm_solve_finish", "spamm_profile_enable",
+           "spamm_profile_read", "spamm_profile_reset")
 KIND_GEMM, KIND_CULL, KIND_PYRAMID = 0, 1, 2
 
 
@@ -79,12 +80,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.ns_sqrt.argtypes = [vp, vp, vp, vp, i64, i64, dbl, dbl, ctypes.c_int, ctypes.POINTER(NsOpts),
                                 ctypes.POINTER(NsResult), vp]
         lib.spamm_ns_history.argtypes = [vp, vp, vp, vp, ctypes.c_int]
+        lib.spamm_solve_footprint.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.spamm_solve_footprint.restype = ctypes.c_size_t
+        lib.spamm_solve_begin.argtypes = [vp, vp, i64, i64, dbl, dbl, ctypes.c_int, ctypes.POINTER(NsOpts),
+                                          ctypes.POINTER(ctypes.c_void_p), vp]
+        lib.spamm_solve_step.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, vp]
+        lib.spamm_solve_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(NsResult)]
+        lib.spamm_solve_finish.argtypes = [vp, vp, vp, vp, i64, vp]
         lib.spamm_profile_enable.argtypes = [vp, ctypes.c_int]
         lib.spamm_profile_reset.argtypes = [vp]
         lib.spamm_profile_read.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
         for f in (lib.spamm_create, lib.spamm_destroy, lib.spamm_norms, lib.spamm_multiply, lib.ns_sqrt,
                   lib.spamm_ns_history, lib.spamm_profile_enable, lib.spamm_profile_reset,
-                  lib.spamm_profile_read):
+                  lib.spamm_profile_read, lib.spamm_solve_begin, lib.spamm_solve_step, lib.spamm_solve_poll,
+                  lib.spamm_solve_finish):
             f.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -199,6 +208,27 @@ class Context:
             info["error"] = self.lib.spamm_last_error().decode()
         return Y, Z, info
 
+    # -- step API (batched and served solves) --------------------------------
+    def footprint(self, n: int, leaf: int, prec="f64", maxit: int = 40) -> int:
+        return int(self.lib.spamm_solve_footprint(n, leaf, _PREC[prec] if isinstance(prec, str) else int(prec),
+                                                  maxit))
+
+    def solve_begin(self, s: torch.Tensor, tau: float, tol: float, maxit: int, leaf: int = 32, prec="f64",
+                    tau_s: float = -1.0, mu_rel: float = 0.0, stagnation_stop: bool = False) -> "Solve":
+        ps, ld = _mat(s, "s")
+        opts = NsOpts(leaf, _PREC[prec] if isinstance(prec, str) else int(prec), float(tau_s), float(mu_rel),
+                      int(bool(stagnation_stop)))
+        h = ctypes.c_void_p()
+        _check(self.lib.spamm_solve_begin(self.handle, ps, s.shape[0], ld, float(tau), float(tol), int(maxit),
+                                          ctypes.byref(opts), ctypes.byref(h), _stream_ptr(s.device)))
+        return Solve(self, h, s.shape[0], s.device)
+
+    def solve_step(self, solves, iterations: int = 1) -> int:
+        """Advance every running solve in the list by `iterations`; returns how many still run."""
+        arr = (ctypes.c_void_p * max(len(solves), 1))(*[x.handle for x in solves])
+        dev = solves[0].device if solves else torch.device("cuda", self.device)
+        return _check(self.lib.spamm_solve_step(self.handle, arr, len(solves), int(iterations), _stream_ptr(dev)))
+
     def profile(self, enable: bool = True):
         _check(self.lib.spamm_profile_enable(self.handle, int(bool(enable))))
 
@@ -222,6 +252,45 @@ class Context:
         m = _check(self.lib.spamm_ns_history(self.handle, r.ctypes.data, t.ctypes.data, nR.ctypes.data, cap))
         m = min(m, cap)
         return r[:m], t[:m], nR[:m]
+
+
+class Solve:
+    """One Newton-Schulz solve on the device (spamm_solve)."""
+
+    def __init__(self, ctx: Context, handle, n: int, device):
+        self.ctx, self.handle, self.n, self.device = ctx, handle, n, device
+
+    def poll(self) -> dict:
+        done = ctypes.c_int(0)
+        res = NsResult()
+        st = self.ctx.lib.spamm_solve_poll(self.handle, ctypes.byref(done), ctypes.byref(res))
+        return dict(done=bool(done.value), status=st, iterations=res.iterations, resid=res.resid,
+                    trace_err=res.trace_err, scale=res.scale, triples_total=res.triples_total,
+                    flops_total=res.flops_total)
+
+    def finish(self, Y: torch.Tensor | None = None, Z: torch.Tensor | None = None, want_outputs: bool = True):
+        """Egress (Y, Z), free the solve; returns (Y, Z, info)."""
+        if self.handle is None:
+            raise RuntimeError("solve already finished")
+        info = self.poll()
+        if want_outputs:
+            if Y is None:
+                Y = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+            if Z is None:
+                Z = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+            py, ld = _mat(Y, "Y")
+            pz, ldz = _mat(Z, "Z")
+            if ldz != ld:
+                raise ValueError("Y and Z must share a leading dimension")
+        else:
+            py = pz = None
+            ld = self.n
+        st = self.ctx.lib.spamm_solve_finish(self.ctx.handle, self.handle, py, pz, ld, _stream_ptr(self.device))
+        self.handle = None
+        info["status"] = st
+        if st < 0:
+            info["error"] = self.ctx.lib.spamm_last_error().decode()
+        return Y, Z, info
 
 
 _default_ctx: dict[int, Context] = {}

@@ -1,0 +1,156 @@
+"""GPU tests of the step API: batched solves of uneven n sharing launches, and
+continuous batching (solves joining and leaving between steps).
+
+Every solve advances through the same kernels whether it runs alone or in a
+mix, one workgroup per output tile with fixed-order reductions, so its result
+must be bitwise identical alone and in any mix; against the FP64 oracle the
+FP64 results must agree to 1e-12 (relative Frobenius) with the same iteration
+count and retained-triple history.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_05856_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1508_05856_amd import spamm
+    c = spamm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def rel(x, ref):
+    return np.linalg.norm(x - ref) / np.linalg.norm(ref)
+
+
+# (kind, n, param, seed, leaf, tau) -- uneven n, both leaf sizes, ragged n
+CASES = [
+    ("kms", 256, 0.7, 0, 32, 1e-8),
+    ("gauss", 300, 1.1, 1, 32, 1e-6),
+    ("kms", 448, 0.85, 2, 64, 1e-6),
+    ("gauss", 700, 1.0, 3, 64, 1e-8),
+    ("kms", 96, 0.6, 4, 32, 1e-4),
+    ("gauss", 1000, 1.2, 5, 64, 1e-6),
+]
+
+
+def make(kind, n, param, seed):
+    spec = dict(kind=kind, n=n, seed=seed, rho=param, h=param)
+    return inputs.build_spec(spec)
+
+
+def solo(ctx, s, leaf, tau, prec="f64"):
+    Y, Z, info = ctx.ns_sqrt(dev(s), tau, 1e-10, 30, leaf=leaf, prec=prec, stagnation_stop=True,
+                             raise_on_error=False)
+    return host(Y), host(Z), info
+
+
+def test_step_api_equals_ns_sqrt(ctx):
+    s = inputs.kms(384, 0.8)
+    Y0, Z0, info0 = solo(ctx, s, 32, 1e-8)
+    sv = ctx.solve_begin(dev(s), 1e-8, 1e-10, 30, leaf=32, stagnation_stop=True)
+    while ctx.solve_step([sv], 1) > 0:
+        pass
+    Y, Z, info = sv.finish()
+    assert info["status"] == info0["status"] and info["iterations"] == info0["iterations"]
+    np.testing.assert_array_equal(host(Y), Y0)
+    np.testing.assert_array_equal(host(Z), Z0)
+
+
+def test_batched_uneven_solves_match_oracle_and_solo(ctx):
+    mats = [make(k, n, p, sd) for (k, n, p, sd, _, _) in CASES]
+    solos = [solo(ctx, s, leaf, tau) for s, (_, _, _, _, leaf, tau) in zip(mats, CASES)]
+    solves = [ctx.solve_begin(dev(s), tau, 1e-10, 30, leaf=leaf, stagnation_stop=True)
+              for s, (_, _, _, _, leaf, tau) in zip(mats, CASES)]
+    steps = 0
+    while ctx.solve_step(solves, 3) > 0:
+        steps += 1
+        assert steps < 40
+    for sv, s, (Ys, Zs, infos), (_, n, _, _, leaf, tau) in zip(solves, mats, solos, CASES):
+        Y, Z, info = sv.finish()
+        Y, Z = host(Y), host(Z)
+        assert info["status"] == infos["status"] and info["iterations"] == infos["iterations"]
+        np.testing.assert_array_equal(Y, Ys)     # alone == in the mix, bitwise
+        np.testing.assert_array_equal(Z, Zs)
+        ores = oracle.ns_sqrt(s, leaf, tau, 1e-10, 30, stagnation_stop=True)
+        r, t, nR = ctx.ns_history()
+        assert info["status"] == ores["status"] and info["iterations"] == ores["iterations"]
+        assert rel(Y, ores["Y"]) <= 1e-12 and rel(Z, ores["Z"]) <= 1e-12
+
+
+def test_continuous_batching_join_and_leave(ctx):
+    mats = [make(k, n, p, sd) for (k, n, p, sd, _, _) in CASES]
+    solos = [solo(ctx, s, leaf, tau) for s, (_, _, _, _, leaf, tau) in zip(mats, CASES)]
+    pending = list(range(len(CASES)))
+    active = {}
+    results = {}
+    tick = 0
+    while pending or active:
+        # admit up to two new solves every other tick
+        if pending and tick % 2 == 0:
+            for _ in range(2):
+                if pending:
+                    i = pending.pop(0)
+                    _, _, _, _, leaf, tau = CASES[i]
+                    active[i] = ctx.solve_begin(dev(mats[i]), tau, 1e-10, 30, leaf=leaf, stagnation_stop=True)
+        order = sorted(active)
+        ctx.solve_step([active[i] for i in order], 1)
+        for i in order:
+            if active[i].poll()["done"]:
+                Y, Z, info = active.pop(i).finish()
+                results[i] = (host(Y), host(Z), info)
+        tick += 1
+        assert tick < 200
+    for i, (Ys, Zs, infos) in enumerate(solos):
+        Y, Z, info = results[i]
+        assert info["iterations"] == infos["iterations"]
+        np.testing.assert_array_equal(Y, Ys)
+        np.testing.assert_array_equal(Z, Zs)
+
+
+def test_batched_fp32_matches_solo(ctx):
+    mats = [inputs.kms(256, 0.7), inputs.gauss_gramian(6, 1.2), inputs.kms(640, 0.6)]
+    solos = [solo(ctx, s, 64, 1e-6, prec="f32") for s in mats]
+    solves = [ctx.solve_begin(dev(s), 1e-6, 1e-10, 30, leaf=64, prec="f32", stagnation_stop=True) for s in mats]
+    while ctx.solve_step(solves, 4) > 0:
+        pass
+    for sv, (Ys, Zs, infos), s in zip(solves, solos, mats):
+        Y, Z, info = sv.finish()
+        np.testing.assert_array_equal(host(Y), Ys)
+        w, V = np.linalg.eigh(s)
+        assert rel(host(Y), (V * np.sqrt(w)) @ V.T) < 1e-3
+
+
+def test_footprint_and_errors(ctx):
+    from paper_1508_05856_amd import spamm
+    fp64 = ctx.footprint(4096, 64, "f64", 40)
+    fp32 = ctx.footprint(4096, 64, "f32", 40)
+    assert fp64 > 5 * 4096 * 4096 * 8 and fp32 > 5 * 4096 * 4096 * 4 and fp32 < fp64
+    assert ctx.footprint(0, 64, "f64", 40) == 0
+    s = inputs.kms(128, 0.5)
+    sv = ctx.solve_begin(dev(s), 1e-6, 1e-10, 10, leaf=32)
+    with pytest.raises(spamm.SpammError):
+        ctx.solve_step([sv, sv], 1)          # a solve may appear once per step
+    with pytest.raises(spamm.SpammError):
+        ctx.solve_step([sv], 0)
+    while ctx.solve_step([sv], 2) > 0:
+        pass
+    assert ctx.solve_step([sv], 1) == 0      # finished solves are skipped
+    _, _, info = sv.finish()
+    assert info["status"] in (0, 1, 2)
