@@ -193,6 +193,13 @@ int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *solve, double *Y, double *Z,
  * number of entries available (iterations + 1), or < 0 on error. */
 int spamm_ns_history(spamm_ctx *ctx, double *r, double *t, int64_t *nR, int cap);
 
+/* Whether spamm_solve_step (and so ns_sqrt) replays each solve set's
+ * iteration as a captured HIP graph (default 1).  The graph is captured on a
+ * stream the context owns, ordered after the caller's stream by an event, and
+ * the caller's stream is ordered after it; steps block the host either way.
+ * While launch timing is enabled, plain launches are used. */
+int spamm_set_graphs(spamm_ctx *ctx, int enable);
+
 /* Launch timing, for measurement.  While enabled, every leaf-product launch
  * (kind 0), cull launch (kind 1) and norm-pyramid launch (kind 2) enqueued
  * through this context is bracketed by a pair of HIP events recorded on the

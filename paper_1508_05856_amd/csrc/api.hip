@@ -98,6 +98,8 @@ struct Plan {
     SolveState *gather_host = nullptr;  // pinned
     int nsolve = 0;
     unsigned long long last_use = 0;
+    hipGraph_t graph = nullptr;         // one captured iteration of this set
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 struct spamm_ctx {
@@ -113,6 +115,9 @@ struct spamm_ctx {
     std::vector<ProfRec> recs;
     std::vector<Plan *> plans;
     unsigned long long next_id = 1, use_clock = 0;
+    bool graphs = true;                   // replay captured iterations when not timing launches
+    hipStream_t gstream = nullptr;        // stream the graphs are captured on and replayed on
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 struct spamm_solve {
@@ -353,6 +358,8 @@ SolveDesc solve_desc(const spamm_solve *s) {
 
 void free_plan(Plan *p) {
     if (!p) return;
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->mem) (void)hipFree(p->mem);
     if (p->gather_host) (void)hipHostFree(p->gather_host);
     delete p;
@@ -453,6 +460,29 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
 
 // Arena layout of one solve; returns its size.  With s non-null, also sets
 // the solve's pointers into s->mem.
+// Captures one iteration of a plan on the context's graph stream.
+int capture_iteration(spamm_ctx *ctx, Plan *p) {
+    hipStream_t st = ctx->gstream;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_iteration(ctx, p, st);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc < 0) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(SPAMM_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(SPAMM_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+    }
+    p->graph = graph;
+    p->graph_exec = exec;
+    return SPAMM_OK;
+}
+
 size_t solve_bytes(const Geom &g, int prec, int maxit, spamm_solve *s) {
     Carve c{s ? s->mem : nullptr, 0};
     const size_t tiles = (size_t)g.nb * g.nb * g.b * g.b * elt_size(prec);
@@ -558,6 +588,18 @@ int spamm_create(spamm_ctx **out, int device) {
         delete ctx;
         return fail(SPAMM_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
     }
+    // default-priority stream for graph capture and replay, and two events
+    // that order it against the caller's stream
+    e = hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+        if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+        (void)hipHostFree(ctx->pinned);
+        delete ctx;
+        return fail(SPAMM_EHIP, "stream/event creation failed: %s", hipGetErrorString(e));
+    }
     *out = ctx;
     return SPAMM_OK;
 }
@@ -569,6 +611,9 @@ int spamm_destroy(spamm_ctx *ctx) {
     for (Plan *p : ctx->plans) free_plan(p);
     ctx->plans.clear();
     for (hipEvent_t e : ctx->pool) HIPCHK(hipEventDestroy(e));
+    if (ctx->gstream) HIPCHK(hipStreamDestroy(ctx->gstream));
+    if (ctx->ev_in) HIPCHK(hipEventDestroy(ctx->ev_in));
+    if (ctx->ev_out) HIPCHK(hipEventDestroy(ctx->ev_out));
     for (int s = 0; s < S_COUNT; ++s)
         if (ctx->buf[s]) HIPCHK(hipFree(ctx->buf[s]));
     if (ctx->pinned) HIPCHK(hipHostFree(ctx->pinned));
@@ -815,14 +860,31 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
         TRY(get_plan(ctx, gr, st, &p));
         plans.push_back(p);
     }
-    for (int it = 0; it < iterations; ++it)
-        for (Plan *p : plans) TRY(enqueue_iteration(ctx, p, st));
-    for (Plan *p : plans) {
-        HIPCHK(launch_gather_states(p->solves, p->nsolve, p->gather, st));
-        HIPCHK(hipMemcpyAsync(p->gather_host, p->gather, p->nsolve * sizeof(SolveState), hipMemcpyDeviceToHost,
-                              st));
+    const bool use_graphs = ctx->graphs && !ctx->prof;
+    if (use_graphs) {
+        // the graph stream waits for the caller's stream, runs the step, and
+        // the caller's stream waits for it (the step also blocks the host)
+        HIPCHK(hipEventRecord(ctx->ev_in, st));
+        HIPCHK(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
+        for (Plan *p : plans)
+            if (!p->graph_exec) TRY(capture_iteration(ctx, p));
+        for (int it = 0; it < iterations; ++it)
+            for (Plan *p : plans) HIPCHK(hipGraphLaunch(p->graph_exec, ctx->gstream));
+    } else {
+        for (int it = 0; it < iterations; ++it)
+            for (Plan *p : plans) TRY(enqueue_iteration(ctx, p, st));
     }
-    HIPCHK(hipStreamSynchronize(st));
+    hipStream_t rs = use_graphs ? ctx->gstream : st;
+    for (Plan *p : plans) {
+        HIPCHK(launch_gather_states(p->solves, p->nsolve, p->gather, rs));
+        HIPCHK(hipMemcpyAsync(p->gather_host, p->gather, p->nsolve * sizeof(SolveState), hipMemcpyDeviceToHost,
+                              rs));
+    }
+    if (use_graphs) {
+        HIPCHK(hipEventRecord(ctx->ev_out, rs));
+        HIPCHK(hipStreamWaitEvent(st, ctx->ev_out, 0));
+    }
+    HIPCHK(hipStreamSynchronize(rs));
     int running = 0;
     for (size_t gi = 0; gi < groups.size(); ++gi)
         for (size_t i = 0; i < groups[gi].size(); ++i) {
@@ -899,6 +961,12 @@ int spamm_ns_history(spamm_ctx *ctx, double *r, double *t, int64_t *nR, int cap)
     if (t) std::memcpy(t, ctx->hist_t.data(), c * sizeof(double));
     if (nR) std::memcpy(nR, ctx->hist_nR.data(), 3 * (size_t)c * sizeof(int64_t));
     return m;
+}
+
+int spamm_set_graphs(spamm_ctx *ctx, int enable) {
+    if (!ctx) return fail(SPAMM_EINVAL, "NULL context");
+    ctx->graphs = enable != 0;
+    return SPAMM_OK;
 }
 
 int spamm_profile_enable(spamm_ctx *ctx, int enable) {

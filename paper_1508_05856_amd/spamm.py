@@ -27,7 +27,7 @@ STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", STAGNATED: "STAGNATED"
 # Every symbol include/spamm.h declares.
 EXPORTS = ("spamm_create", "spamm_destroy", "spamm_last_error", "spamm_pyramid_len", "spamm_norms",
            "spamm_multiply", "ns_sqrt", "spamm_ns_history", "spamm_solve_footprint", "spamm_solve_begin",
-           "spamm_solve_step", "spamm_solve_poll", "spamm_solve_finish", "spamm_profile_enable",
+           "spamm_solve_step", "spamm_solve_poll", "spamm_solve_finish", "spamm_set_graphs", "spamm_profile_enable",
            "spamm_profile_read", "spamm_profile_reset")
 KIND_GEMM, KIND_CULL, KIND_PYRAMID = 0, 1, 2
 
@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.spamm_solve_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(NsResult)]
         lib.spamm_solve_finish.argtypes = [vp, vp, vp, vp, i64, vp]
         lib.spamm_profile_enable.argtypes = [vp, ctypes.c_int]
+        lib.spamm_set_graphs.argtypes = [vp, ctypes.c_int]
+        lib.spamm_set_graphs.restype = ctypes.c_int
         lib.spamm_profile_reset.argtypes = [vp]
         lib.spamm_profile_read.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
         for f in (lib.spamm_create, lib.spamm_destroy, lib.spamm_norms, lib.spamm_multiply, lib.ns_sqrt,
@@ -228,6 +230,9 @@ class Context:
         arr = (ctypes.c_void_p * max(len(solves), 1))(*[x.handle for x in solves])
         dev = solves[0].device if solves else torch.device("cuda", self.device)
         return _check(self.lib.spamm_solve_step(self.handle, arr, len(solves), int(iterations), _stream_ptr(dev)))
+
+    def set_graphs(self, enable: bool = True):
+        _check(self.lib.spamm_set_graphs(self.handle, int(bool(enable))))
 
     def profile(self, enable: bool = True):
         _check(self.lib.spamm_profile_enable(self.handle, int(bool(enable))))

@@ -154,3 +154,34 @@ def test_footprint_and_errors(ctx):
     assert ctx.solve_step([sv], 1) == 0      # finished solves are skipped
     _, _, info = sv.finish()
     assert info["status"] in (0, 1, 2)
+
+
+def test_graph_replays_equal_plain_launches(ctx):
+    """Each step replays a captured iteration several times, with the engine's
+    own eager read-back between steps; every result must equal the plain-launch
+    result bitwise."""
+    mats = [make(k, n, p, sd) for (k, n, p, sd, _, _) in CASES[:4]]
+
+    def run(graphs):
+        ctx.set_graphs(graphs)
+        solves = [ctx.solve_begin(dev(s), tau, 1e-10, 30, leaf=leaf, stagnation_stop=True)
+                  for s, (_, _, _, _, leaf, tau) in zip(mats, CASES[:4])]
+        while ctx.solve_step(solves, 2) > 0:
+            pass
+        out = []
+        for sv in solves:
+            Y, Z, info = sv.finish()
+            out.append((host(Y), host(Z), info["iterations"]))
+        return out
+
+    try:
+        a = run(True)
+        b = run(False)
+        c = run(True)
+    finally:
+        ctx.set_graphs(True)
+    for (ya, za, ka), (yb, zb, kb), (yc, zc, kc) in zip(a, b, c):
+        assert ka == kb == kc
+        np.testing.assert_array_equal(ya, yb)
+        np.testing.assert_array_equal(za, zb)
+        np.testing.assert_array_equal(ya, yc)
