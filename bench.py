@@ -43,8 +43,12 @@ def parse():
     p.add_argument("--cpu-sample-iters", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--dump-launches", default=None, help="write per-launch (flops, ms) of the timed steps")
-    p.add_argument("--workload", default="gauss4096", choices=["gauss4096", "batched"],
-                   help="gauss4096: the n=4096 Gaussian Gramian (default); batched: 64 uneven solves together")
+    p.add_argument("--workload", default="gauss4096", choices=["gauss4096", "batched", "serving"],
+                   help="gauss4096: the n=4096 Gaussian Gramian (default); batched: 64 uneven solves "
+                        "together; serving: a Poisson request stream through the continuous-batching server")
+    p.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    p.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
+    p.add_argument("--nmax", type=int, default=16384, help="serving: largest n (log-uniform from 512)")
     p.add_argument("--iters-per-step", type=int, default=4, help="batched: iterations per synchronisation")
     return p.parse_args()
 
@@ -138,6 +142,103 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def run_serving(args):
+    """Poisson arrivals of sqrt / inverse-sqrt requests (n log-uniform in
+    [512, nmax], KMS and Gaussian, tau in {1e-4, 1e-6, 1e-8}, tol 1e-8, FP64)
+    submitted in real time to the continuous-batching server; latency is
+    arrival to result on the device."""
+    import threading
+
+    import torch
+
+    from paper_1508_05856_amd import inputs, serve
+
+    reqs = inputs.serving_requests(args.rate, args.duration, seed=0, nmin=512, nmax=args.nmax)
+    dev = torch.device("cuda:0")
+    srv = serve.Server(0, iters_per_step=args.iters_per_step)
+    # warm up kernels and tables on a tiny stream
+    for f in [srv.submit(inputs.kms_device(n, 0.7, dev), 1e-6, 1e-8, leaf=64) for n in (512, 1024)]:
+        f.result()
+    futures = [None] * len(reqs)
+    done = [0]
+    t0 = time.perf_counter()
+
+    def on_done(f):
+        # keep the timing and status; drop Y, Z so finished outputs do not pile up in HBM
+        if f.exception() is None:
+            res = f.result()
+            res.Y = res.Z = None
+        done[0] += 1
+        if done[0] % 100 == 0 or done[0] == len(reqs):
+            print(f"served {done[0]}/{len(reqs)} at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    def client():
+        # inputs are materialised on the device at arrival; when the queue of
+        # unadmitted requests is deep (offered load above capacity) the client
+        # holds back so queued inputs cannot exhaust HBM.  Latency is measured
+        # from the scheduled arrival, so holding back never hides queueing.
+        for i, r in enumerate(reqs):
+            delay = r["t"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            while True:
+                cnt, nbytes = srv.backlog()
+                if cnt < 32 and nbytes < (16 << 30):
+                    break
+                time.sleep(0.0005)
+            s = inputs.build_spec_device(r, dev)
+            f = srv.submit(s, r["tau"], 1e-8, maxit=40, leaf=64, prec="f64", tau_s=0.01 * r["tau"],
+                           stagnation_stop=True)
+            f.add_done_callback(on_done)
+            futures[i] = f
+            del s
+
+    err = []
+
+    def client_guarded():
+        try:
+            client()
+        except BaseException as e:
+            err.append(e)
+
+    th = threading.Thread(target=client_guarded)
+    th.start()
+    th.join()
+    if err:
+        srv.close()
+        raise err[0]
+    results, failed = [], 0
+    for f, r in zip(futures, reqs):
+        try:
+            results.append((f.result(timeout=600), r))
+        except Exception as e:
+            failed += 1
+            print(f"request n={r['n']} failed: {e}", file=sys.stderr, flush=True)
+    t_end = time.perf_counter() - t0
+    stats = dict(srv.stats)
+    srv.close()
+    lat = np.array([res.t_done - (t0 + r["t"]) for res, r in results])
+    statuses = [res.info["status"] for res, _ in results]
+    line = {
+        "metric": "NS sqrt serving: solves/sec and p50/p99 latency under Poisson arrivals",
+        "value": len(results) / t_end, "unit": "solves/s", "n_gpus": 1, "steps": len(results), "warmup": 2,
+        "ms_per_step": t_end * 1e3 / len(results), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": f"serving_poisson_{args.rate:g}rps_{args.duration:g}s_n512-{args.nmax}",
+            "requests": len(reqs), "failed": failed, "offered_rate": args.rate, "duration_s": args.duration,
+            "makespan_s": t_end, "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
+            "tol": 1e-8, "tau_s": "0.01 tau", "stop": "stagnation", "iters_per_step": args.iters_per_step,
+            "sizes_n": [int(min(r["n"] for r in reqs)), int(max(r["n"] for r in reqs))],
+            "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
+            "useful_tflops": sum(res.info["flops_total"] for res, _ in results) / t_end / 1e12,
+            "engine": stats,
+        },
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -146,6 +247,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "serving":
+        run_serving(args)
         return
 
     import torch

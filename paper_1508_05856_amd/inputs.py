@@ -188,3 +188,42 @@ def serving_requests(rate: float = 200.0, duration: float = 60.0, seed: int = 0,
             reqs.append(dict(t=t, kind="gauss", n=n, h=float(rng.uniform(0.8, 1.2)), tau=tau, seed=i))
         i += 1
     return reqs
+
+
+# ---------------------------------------------------------------------------
+# Device-side construction for serving-scale inputs (n up to 16384, where
+# building on the host would dominate).  Same seeded positions; the Gramian is
+# formed on the GPU in row chunks, exactly symmetric.
+# ---------------------------------------------------------------------------
+
+def kms_device(n: int, rho: float, device):
+    import torch
+    idx = torch.arange(n, device=device, dtype=torch.float64)
+    return torch.pow(torch.tensor(float(rho), dtype=torch.float64, device=device),
+                     (idx[:, None] - idx[None, :]).abs())
+
+
+def gramian_device(pos: np.ndarray, device, rows_per_chunk: int = 2048):
+    import torch
+    p = torch.from_numpy(np.ascontiguousarray(pos)).to(device)
+    n = p.shape[0]
+    out = torch.empty((n, n), dtype=torch.float64, device=device)
+    for r0 in range(0, n, rows_per_chunk):
+        r1 = min(n, r0 + rows_per_chunk)
+        dx = p[r0:r1, 0:1] - p[None, :, 0]
+        dy = p[r0:r1, 1:2] - p[None, :, 1]
+        dz = p[r0:r1, 2:3] - p[None, :, 2]
+        d2 = dx * dx
+        d2 += dy * dy
+        d2 += dz * dz
+        d2 *= -0.5
+        torch.exp(d2, out=out[r0:r1])
+    return out
+
+
+def build_spec_device(spec: dict, device):
+    """Materialise one batched/serving instance directly on the device."""
+    if spec["kind"] == "kms":
+        return kms_device(spec["n"], spec["rho"], device)
+    m = smallest_cube(spec["n"])
+    return gramian_device(gauss_positions(m, spec["h"], 0.1, spec["seed"], spec["n"]), device)

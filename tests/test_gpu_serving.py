@@ -1,0 +1,105 @@
+"""GPU tests of the continuous-batching server.
+
+Requests submitted while others are on the device join them at a step
+boundary and share their launches; each result must be bitwise the one the
+same request gets when solved alone (same kernels, one workgroup per output
+tile, fixed-order reductions), and admission must respect the memory budget.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1508_05856_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (kind, n, param, seed, leaf, tau)
+REQS = [
+    ("kms", 320, 0.7, 0, 32, 1e-8),
+    ("gauss", 500, 1.0, 1, 64, 1e-6),
+    ("kms", 777, 0.85, 2, 64, 1e-4),
+    ("gauss", 216, 1.2, 3, 32, 1e-8),
+    ("gauss", 900, 0.9, 4, 64, 1e-8),
+    ("kms", 130, 0.5, 5, 32, 1e-6),
+    ("gauss", 1331, 1.1, 6, 64, 1e-6),
+    ("kms", 1024, 0.9, 7, 64, 1e-8),
+]
+
+
+def mat(kind, n, param, seed):
+    return torch.from_numpy(inputs.build_spec(dict(kind=kind, n=n, seed=seed, rho=param, h=param))).cuda()
+
+
+@pytest.fixture(scope="module")
+def solo_results():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1508_05856_amd import spamm
+    ctx = spamm.Context(0)
+    out = []
+    for kind, n, p, sd, leaf, tau in REQS:
+        Y, Z, info = ctx.ns_sqrt(mat(kind, n, p, sd), tau, 1e-8, 40, leaf=leaf, stagnation_stop=True,
+                                 raise_on_error=False)
+        out.append((Y.cpu().numpy(), Z.cpu().numpy(), info))
+    ctx.close()
+    return out
+
+
+def test_requests_joining_a_running_mix_match_solo(solo_results):
+    from paper_1508_05856_amd import serve
+    srv = serve.Server(0, iters_per_step=1, autostart=False)
+    futs = {}
+    for i in range(3):  # queued before the engine starts: admitted together
+        kind, n, p, sd, leaf, tau = REQS[i]
+        futs[i] = srv.submit(mat(kind, n, p, sd), tau, 1e-8, maxit=40, leaf=leaf, stagnation_stop=True)
+    srv.start()
+
+    def client():
+        while srv.stats["steps"] < 2:   # the rest arrive while the first ones are on the device
+            time.sleep(0.001)
+        for i in range(3, len(REQS)):
+            kind, n, p, sd, leaf, tau = REQS[i]
+            futs[i] = srv.submit(mat(kind, n, p, sd), tau, 1e-8, maxit=40, leaf=leaf, stagnation_stop=True)
+            time.sleep(0.002)
+
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    results = {i: f.result(timeout=120) for i, f in futs.items()}
+    stats = dict(srv.stats)
+    srv.close()
+    assert stats["completed"] == len(REQS) and stats["max_active"] >= 3
+    for i, (Ys, Zs, infos) in enumerate(solo_results):
+        r = results[i]
+        assert r.info["status"] == infos["status"] and r.info["iterations"] == infos["iterations"], i
+        np.testing.assert_array_equal(r.Y.cpu().numpy(), Ys)
+        np.testing.assert_array_equal(r.Z.cpu().numpy(), Zs)
+        assert r.latency_s >= r.queued_s >= 0.0
+
+
+def test_admission_by_footprint(solo_results):
+    from paper_1508_05856_amd import serve
+    probe = serve.Server(0, autostart=False)
+    fp = [probe.ctx.footprint(REQS[i][1], REQS[i][4], "f64", 40) for i in (4, 6)]
+    probe.close()
+    # room for either request alone but not both: they must run one after the other
+    srv = serve.Server(0, hbm_budget=max(fp) + min(fp) // 2, iters_per_step=2, autostart=False)
+    futs = []
+    for i in (4, 6):
+        kind, n, p, sd, leaf, tau = REQS[i]
+        futs.append(srv.submit(mat(kind, n, p, sd), tau, 1e-8, maxit=40, leaf=leaf, stagnation_stop=True))
+    too_big = srv.submit(mat("kms", 4096, 0.7, 0), 1e-6, 1e-8, leaf=64)
+    srv.start()
+    res = [f.result(timeout=120) for f in futs]
+    stats = dict(srv.stats)
+    srv.close()
+    with pytest.raises(ValueError):
+        too_big.result(timeout=1)
+    assert stats["max_active"] == 1 and stats["completed"] == 2
+    assert stats["peak_bytes"] <= max(fp) + min(fp) // 2
+    for r, i in zip(res, (4, 6)):
+        np.testing.assert_array_equal(r.Y.cpu().numpy(), solo_results[i][0])
+        np.testing.assert_array_equal(r.Z.cpu().numpy(), solo_results[i][1])
