@@ -51,7 +51,9 @@ int fail(int code, const char *fmt, ...) {
 bool valid_leaf(int b) { return b == 16 || b == 32 || b == 64; }
 bool valid_prec(int p) { return p == SPAMM_F64 || p == SPAMM_F32 || p == SPAMM_BF16X3; }
 size_t elt_size(int prec) { return prec == SPAMM_F64 ? 8 : 4; }
+// storage type of the tiles: BF16x3 keeps FP32 operands and splits them inside the leaf product
 int kernel_prec(int prec) { return prec == SPAMM_F64 ? P_F64 : P_F32; }
+int gemm_prec(int prec) { return prec == SPAMM_F64 ? P_F64 : (prec == SPAMM_BF16X3 ? P_BF16X3 : P_F32); }
 constexpr int MAX_NB = 1024;  // the pyramid's two passes cover P <= 1024
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -447,12 +449,12 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
     const int kp = kernel_prec(p->prec);
     TIMED(K_CULL, launch_cull_tab(p->tx, st));
     HIPCHK(launch_plan_tab(p->tx, p->leaf, (int)elt_size(p->prec), st));
-    TIMED(K_GEMM, launch_gemm_tab(kp, p->leaf, p->tx, st));
+    TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
     HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
     TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
     TIMED(K_CULL, launch_cull_tab(p->tyz, st));
     HIPCHK(launch_plan_tab(p->tyz, p->leaf, (int)elt_size(p->prec), st));
-    TIMED(K_GEMM, launch_gemm_tab(kp, p->leaf, p->tyz, st));
+    TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tyz, st));
     TIMED(K_PYR, launch_pyramid_tab(p->tyz, st));
     HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
     return SPAMM_OK;
@@ -537,7 +539,7 @@ int validate_ns(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, double t
     if (!(tol > 0.0)) return fail(SPAMM_EINVAL, "tol must be > 0");
     if (maxit < 0 || maxit > 100000) return fail(SPAMM_EINVAL, "maxit must be in [0, 100000]");
     if (!valid_prec(o.prec)) return fail(SPAMM_EINVAL, "unknown precision %d", o.prec);
-    if (o.prec == SPAMM_BF16X3) return fail(SPAMM_EINVAL, "BF16x3 leaves are not available in this build");
+    if (o.prec == SPAMM_BF16X3 && o.leaf == 16) return fail(SPAMM_EINVAL, "BF16x3 leaves need leaf 32 or 64");
     if (!(o.mu_rel >= 0.0) || std::isinf(o.mu_rel)) return fail(SPAMM_EINVAL, "mu_rel must be finite and >= 0");
     if (std::isnan(o.tau_s) || std::isinf(o.tau_s)) return fail(SPAMM_EINVAL, "tau_s must be finite");
     return SPAMM_OK;
@@ -657,7 +659,7 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     if (!B || !C) return fail(SPAMM_EINVAL, "NULL matrix pointer");
     if (!(tau >= 0.0) || std::isinf(tau)) return fail(SPAMM_EINVAL, "tau must be finite and >= 0");
     if (!valid_prec(prec)) return fail(SPAMM_EINVAL, "unknown precision %d", prec);
-    if (prec == SPAMM_BF16X3) return fail(SPAMM_EINVAL, "BF16x3 leaves are not available in this build");
+    if (prec == SPAMM_BF16X3 && leaf == 16) return fail(SPAMM_EINVAL, "BF16x3 leaves need leaf 32 or 64");
     if (triples && cap < 0) return fail(SPAMM_EINVAL, "negative triple capacity");
     TRY(enter(ctx));
     hipStream_t st = (hipStream_t)stream;
@@ -711,7 +713,7 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     HIPCHK(hipMemcpyAsync(ctx->buf[S_TAB], image.data(), image.size(), hipMemcpyHostToDevice, st));
     TIMED(K_CULL, launch_cull_tab(t, st));
     HIPCHK(launch_plan_tab(t, leaf, (int)elt_size(prec), st));
-    TIMED(K_GEMM, launch_gemm_tab(kp, leaf, t, st));
+    TIMED(K_GEMM, launch_gemm_tab(gemm_prec(prec), leaf, t, st));
     HIPCHK(launch_egress(kp, g, ctx->buf[S_T2], C, ld, 1.0, 0, st));
     int status = SPAMM_OK;
     if (stats || triples) {

@@ -124,10 +124,11 @@ def test_continuous_batching_join_and_leave(ctx):
         np.testing.assert_array_equal(Z, Zs)
 
 
-def test_batched_fp32_matches_solo(ctx):
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_batched_reduced_precision_matches_solo(ctx, prec):
     mats = [inputs.kms(256, 0.7), inputs.gauss_gramian(6, 1.2), inputs.kms(640, 0.6)]
-    solos = [solo(ctx, s, 64, 1e-6, prec="f32") for s in mats]
-    solves = [ctx.solve_begin(dev(s), 1e-6, 1e-10, 30, leaf=64, prec="f32", stagnation_stop=True) for s in mats]
+    solos = [solo(ctx, s, 64, 1e-6, prec=prec) for s in mats]
+    solves = [ctx.solve_begin(dev(s), 1e-6, 1e-10, 30, leaf=64, prec=prec, stagnation_stop=True) for s in mats]
     while ctx.solve_step(solves, 4) > 0:
         pass
     for sv, (Ys, Zs, infos), s in zip(solves, solos, mats):

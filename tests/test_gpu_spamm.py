@@ -140,6 +140,32 @@ def test_multiply_f32_error_vs_oracle(ctx):
     assert err < 1e-6
 
 
+@pytest.mark.parametrize("n,leaf", [(500, 32), (640, 64), (64, 64)])
+def test_multiply_bf16x3_error_vs_oracle(ctx, n, leaf):
+    """BF16x3 leaves: operands are stored in FP32, so the cull sees the FP32
+    values and R must equal the oracle's R on the FP32-rounded inputs.  Each
+    retained term a*b is computed as hi*hi + hi*lo + lo*hi with |a - hi - lo| <=
+    2^-17 |a| and |lo| <= 2^-9 |a|, so per term the error is below 2^-15 |a||b|,
+    plus FP32 accumulation; the bound used is 2^-13 sum_R |A_ik||B_kj|
+    elementwise (the oracle's SpAMM of |A|, |B| has the same norms, hence the
+    same R).  A single bf16 product would be ~2^-9 off, so the Frobenius error
+    must also be far below that."""
+    tau = 1e-6
+    a = decaying(n, seed=17, rate=0.05).astype(np.float32).astype(np.float64)
+    b = decaying(n, seed=18, rate=0.05).astype(np.float32).astype(np.float64)
+    C, st, trip = ctx.spamm_multiply(dev(a), dev(b), tau, leaf, prec="bf16x3", triples=True)
+    Co, Ro, cnt = oracle.spamm(a, b, leaf, tau, want_triples=True)
+    Cabs, _, _ = oracle.spamm(np.abs(a), np.abs(b), leaf, tau, want_triples=False)
+    assert st["retained"] == cnt
+    ties = near_tie_mask(a, b, leaf, tau)
+    got = {tuple(t) for t in host(trip).tolist() if not ties[t[0], t[1], t[2]]}
+    exp = {tuple(t) for t in np.asarray(Ro).tolist() if not ties[t[0], t[1], t[2]]}
+    assert got == exp
+    err = np.abs(host(C) - Co)
+    assert np.all(err <= 2.0 ** -13 * Cabs + 1e-300)
+    assert rel(host(C), Co) < 1e-5
+
+
 # ---------------------------------------------------------------------------
 # Newton-Schulz
 # ---------------------------------------------------------------------------
@@ -343,3 +369,23 @@ def test_ns_f32_leaves_error_vs_fp64_oracle(ctx):
     ey, ez = rel(host(Y), ores["Y"]), rel(host(Z), ores["Z"])
     print(f"f32 leaves: relY={ey:.2e} relZ={ez:.2e} iterations {info['iterations']} vs {ores['iterations']}")
     assert ey <= 5e-6 and ez <= 5e-6
+
+
+@pytest.mark.parametrize("kind", ["kms", "gauss"])
+def test_ns_bf16x3_leaves_error_vs_fp64_oracle(ctx, kind):
+    """Two bf16 pieces carry a 16-bit significand, so each product is off by
+    O(2^-16) relative; the inverse root amplifies relative perturbations of s
+    by up to sqrt(kappa).  Bound: sqrt(kappa) 2^-16 (KMS: kappa 32; the
+    Gaussian lattice m=8, h=1: kappa 2.1e4).  A dropped cross term would be
+    O(2^-8) and fail it."""
+    s = inputs.kms(512, 0.7) if kind == "kms" else inputs.gauss_gramian(8, 1.0)
+    w = np.linalg.eigvalsh(s)
+    bound = np.sqrt(w[-1] / w[0]) * 2.0 ** -16
+    leaf = 32 if kind == "kms" else 64
+    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-8, 1e-5, 40, leaf=leaf, prec="bf16x3", stagnation_stop=True)
+    ores = oracle.ns_sqrt(s, leaf, 1e-8, 1e-5, 40, stagnation_stop=True)
+    ey, ez = rel(host(Y), ores["Y"]), rel(host(Z), ores["Z"])
+    print(f"bf16x3 leaves ({kind}): relY={ey:.2e} relZ={ez:.2e} iterations {info['iterations']} "
+          f"vs {ores['iterations']}")
+    assert info["status"] in (0, 2)
+    assert ey <= bound and ez <= bound
