@@ -56,7 +56,7 @@ def _load():
             lib.oracle_ns_step.argtypes = [dp, dp, dp, dp, i64, i64, ctypes.c_double, ctypes.c_double]
             lib.oracle_ns_sqrt.argtypes = [dp, dp, dp, i64, i64, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                           dp, dp, lp, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.c_int, dp, dp, lp, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_double)]
             for f in (lib.oracle_norms, lib.oracle_spamm, lib.oracle_spamm_tiles, lib.oracle_ns_sqrt,
                       lib.oracle_ns_step):
@@ -144,9 +144,10 @@ def spamm_tiles(a, b, leaf: int, tau: float, tiles):
 
 
 def ns_sqrt(s, leaf: int, tau: float, tol: float, maxit: int, tau_s: float = -1.0, mu_rel: float = 0.0,
-            stagnation_stop: bool = False) -> dict:
-    """Dual-channel coupled Newton-Schulz.  Returns a dict with Y, Z, status,
-    iterations, scale and the r, t and |R| histories."""
+            stagnation_stop: bool = False, damped: bool = False) -> dict:
+    """Dual-channel coupled Newton-Schulz (optionally with the damped map of
+    Sec. 4.3).  Returns a dict with Y, Z, status, iterations, scale and the r,
+    t and |R| histories."""
     s = _f64(s)
     n = s.shape[0]
     lib = _load()
@@ -158,7 +159,8 @@ def ns_sqrt(s, leaf: int, tau: float, tol: float, maxit: int, tau_s: float = -1.
     it = ctypes.c_int(0)
     sc = ctypes.c_double(0.0)
     st = lib.oracle_ns_sqrt(_dptr(s), _dptr(Y), _dptr(Z), n, leaf, float(tau), float(tau_s), float(tol),
-                            int(maxit), float(mu_rel), int(bool(stagnation_stop)), _dptr(r), _dptr(t),
+                            int(maxit), float(mu_rel), int(bool(stagnation_stop)), int(bool(damped)),
+                            _dptr(r), _dptr(t),
                             nr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(it),
                             ctypes.byref(sc))
     k = it.value

@@ -374,16 +374,45 @@ static int check_input(const double *s, int64_t n) {
     return ORC_OK;
 }
 
-/* One dual-channel update (Sec. 3.2, eq. "cannonical", alpha = 1): x holds
- * x_k = y_k (x)_tau z_k on entry and h_k = 1.5 I_n - 0.5 x_k on exit;
- * yn = h_k (x)_{tau_s} y_k, zn = z_k (x)_tau h_k. */
+/* Damping of the map (Sec. 4.3 "Mapping"): the scaling
+ *   alpha(t) = 1 + 1.85 / (1 + exp(-50 (t - 0.35)))
+ * and the stabilisation eps(t) = 0.1 / (1 + exp(-75 (t - 0.30))), both driven
+ * by the relative trace error t_k.  The paper turns both off towards
+ * convergence through the sigmoids, which never reach 1 and 0 exactly; an eps
+ * of 1.7e-11 at t = 0 would move the fixed point to x = (1-eps)/(1-2eps) and
+ * put a floor of sqrt(n) eps under r_k.  Reading: both are switched off
+ * (alpha = 1, eps = 0) once t_k < 0.1, where eps < 3.1e-8 and alpha - 1 < 7e-6. */
+static void damping(int damped, double t, double *alpha, double *eps) {
+    if (damped && t >= 0.1) {
+        *alpha = 1.0 + 1.85 / (1.0 + exp(-50.0 * (t - 0.35)));
+        *eps = 0.1 / (1.0 + exp(-75.0 * (t - 0.30)));
+    } else {
+        *alpha = 1.0;
+        *eps = 0.0;
+    }
+}
+
+/* One dual-channel update (Sec. 3.2, eq. "cannonical"): x holds
+ * x_k = y_k (x)_tau z_k on entry and h_k on exit, then
+ * yn = h_k (x)_{tau_s} y_k, zn = z_k (x)_tau h_k.
+ * Undamped (alpha = 1, eps = 0): h_k = 1.5 I_n - 0.5 x_k.  Damped: the
+ * stabilising map [0,1] -> [eps, 1-eps], xs = eps I_n + (1 - 2 eps) x_k, then
+ * the scaled logistic h_alpha[xs] = (sqrt(alpha)/2) (3 I_n - alpha xs). */
 static void ns_update(qmat *x, const qmat *y, const qmat *z, qmat *yn, qmat *zn, double tau, double tau_s,
-                      int64_t *ny, int64_t *nz) {
+                      double alpha, double eps, int64_t *ny, int64_t *nz) {
     const int64_t n = x->n, np = x->np;
+    const int plain = (alpha == 1.0 && eps == 0.0);
+    const double half_sqrt_alpha = 0.5 * sqrt(alpha);
     for (int64_t i = 0; i < np; i++)
         for (int64_t j = 0; j < np; j++) {
             const double v = x->a[i * np + j];
-            x->a[i * np + j] = ((i == j && i < n) ? 1.5 : 0.0) - 0.5 * v;
+            const int diag = (i == j && i < n);
+            if (plain) {
+                x->a[i * np + j] = (diag ? 1.5 : 0.0) - 0.5 * v;
+            } else {
+                const double xs = (diag ? eps : 0.0) + (1.0 - 2.0 * eps) * v;
+                x->a[i * np + j] = half_sqrt_alpha * ((diag ? 3.0 : 0.0) - alpha * xs);
+            }
         }
     qmat_norms(x);
     *ny = spamm(x, y, yn, tau_s, NULL, 0);
@@ -409,7 +438,7 @@ int oracle_ns_step(const double *y_in, const double *z_in, double *y_out, double
     qmat_norms(&z);
     int64_t ny, nz;
     spamm(&y, &z, &x, tau, NULL, 0);
-    ns_update(&x, &y, &z, &yn, &zn, tau, tau_s, &ny, &nz);
+    ns_update(&x, &y, &z, &yn, &zn, tau, tau_s, 1.0, 0.0, &ny, &nz);
     store_logical(&yn, y_out, n);
     store_logical(&zn, z_out, n);
     qmat_free(&y);
@@ -429,11 +458,19 @@ int oracle_ns_step(const double *y_in, const double *z_in, double *y_out, double
  *     r_k < tol                       -> OK, return (y_k, z_k)
  *     r_k not finite or
  *       r_k > 10 max(r_0, sqrt(n))    -> DIVERGED
- *     stagnation_stop and r_k >= .99 r_{k-1} >= .99^2 r_{k-2}... (two
- *       consecutive non-decreases by 1%) -> STAGNATED (outputs valid)
+ *     stagnation_stop and, on two consecutive k, r_best < 1/2 and
+ *       r_k >= .99 r_best, r_best = min(r_0 .. r_{k-1})
+ *                                     -> STAGNATED (outputs valid)
+ *       (with r < 1/2 every eigenvalue x of x has |1 - x| < 1/2, where one
+ *       exact update maps 1 - x to (1 - x)^2 (2 + x)/4, at most 0.44 (1 - x):
+ *       two updates that fail to gain 1% on the best residual are the
+ *       tau/rounding floor, not the slow start of an ill-conditioned
+ *       iteration; the best, not the previous, residual keeps a fluctuating
+ *       floor from resetting the count)
  *     k == maxit                      -> NOT_CONVERGED (outputs valid)
- *     h_k = (3 I_n - x_k)/2 ;  y_{k+1} = h_k (x)_{tau_s} y_k ;
- *     z_{k+1} = z_k (x)_tau h_k
+ *     h_k = (3 I_n - x_k)/2, or with damping the map of damping() and
+ *       ns_update() at alpha(t_k), eps(t_k);
+ *     y_{k+1} = h_k (x)_{tau_s} y_k ;  z_{k+1} = z_k (x)_tau h_k
  *   Returned: Y = sqrt(c) y_k, Z = z_k / sqrt(c) (logical n x n).
  *
  * Histories (optional, capacity maxit+1 entries): r_hist[k], t_hist[k],
@@ -441,8 +478,8 @@ int oracle_ns_step(const double *y_in, const double *z_in, double *y_out, double
  * update followed).  *iters = number of (y, z) updates performed.
  */
 int oracle_ns_sqrt(const double *s, double *Y, double *Z, int64_t n, int64_t b, double tau, double tau_s,
-                   double tol, int maxit, double mu_rel, int stagnation_stop, double *r_hist, double *t_hist,
-                   int64_t *nR_hist, int *iters, double *scale) {
+                   double tol, int maxit, double mu_rel, int stagnation_stop, int damped, double *r_hist,
+                   double *t_hist, int64_t *nR_hist, int *iters, double *scale) {
     if (n <= 0 || b <= 0 || !(tau >= 0.0) || !(tol > 0.0) || maxit < 0 || !(mu_rel >= 0.0)) return ORC_EINVAL;
     if (tau_s < 0.0) tau_s = tau;
     int st = check_input(s, n);
@@ -475,7 +512,7 @@ int oracle_ns_sqrt(const double *s, double *Y, double *Z, int64_t n, int64_t b, 
 
     int status = ORC_NOT_CONVERGED;
     int k = 0;
-    double r0 = 0.0, r_prev = 0.0;
+    double r0 = 0.0, r_best = 0.0;
     int nondecrease = 0;
     for (k = 0;; k++) {
         int64_t nx = spamm(&y, &z, &x, tau, NULL, 0);
@@ -497,13 +534,15 @@ int oracle_ns_sqrt(const double *s, double *Y, double *Z, int64_t n, int64_t b, 
         if (r < tol) { status = ORC_OK; break; }
         if (!isfinite(r) || r > 10.0 * fmax(r0, sqrt((double)n))) { status = ORC_EDIVERGED; break; }
         if (stagnation_stop && k > 0) {
-            nondecrease = (r >= 0.99 * r_prev) ? nondecrease + 1 : 0;
+            nondecrease = (r_best < 0.5 && r >= 0.99 * r_best) ? nondecrease + 1 : 0;
             if (nondecrease >= 2) { status = ORC_STAGNATED; break; }
         }
-        r_prev = r;
+        if (k == 0 || r < r_best) r_best = r;
         if (k == maxit) { status = ORC_NOT_CONVERGED; break; }
         int64_t ny, nz;
-        ns_update(&x, &y, &z, &yn, &zn, tau, tau_s, &ny, &nz);
+        double alpha, eps;
+        damping(damped, t, &alpha, &eps);
+        ns_update(&x, &y, &z, &yn, &zn, tau, tau_s, alpha, eps, &ny, &nz);
         if (nR_hist) { nR_hist[3 * k + 1] = ny; nR_hist[3 * k + 2] = nz; }
         qmat tmp = y; y = yn; yn = tmp;
         tmp = z; z = zn; zn = tmp;

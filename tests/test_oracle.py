@@ -395,6 +395,26 @@ def test_ns_c1_stalls_and_stagnation_stop():
     assert rel(lit["Y"], Yr) < 1e-5 and rel(lit["Z"], Zr) < 1e-5
 
 
+def test_stagnation_stop_ignores_the_slow_start():
+    """An ill-conditioned start moves r by well under 1% per update while the
+    small eigenvalues grow by 9/4 per update; the stall rule must not fire
+    there (it only counts once r_{k-1} < 1/2).  Diagonal s' with one unit
+    eigenvalue and 255 at 1e-4, tau = 0: exact NS, so the iteration must reach
+    tol, with the update count of the scalar recurrence x <- x (3 - x)^2 / 4."""
+    d = np.full(256, 1e-4)
+    d[0] = 1.0
+    s = np.diag(d)
+    res = oracle.ns_sqrt(s, 16, 0.0, 1e-10, 60, stagnation_stop=True)
+    assert res["status"] == oracle.OK
+    assert res["r"][1] >= 0.99 * res["r"][0] and res["r"][2] >= 0.99 * res["r"][1]  # a slow start
+    x, k = d.copy(), 0
+    while np.sqrt(np.sum((1 - x) ** 2)) >= 1e-10:
+        x = x * (3 - x) ** 2 / 4
+        k += 1
+    assert res["iterations"] == k
+    np.testing.assert_allclose(np.diag(res["Y"]), np.sqrt(d), rtol=1e-12)
+
+
 def test_ns_status_codes():
     s = inputs.kms(64, 0.6)
     bad = s.copy()
@@ -413,3 +433,72 @@ def test_ns_status_codes():
     np.testing.assert_allclose(r0["Z"], np.eye(64) / np.sqrt(c), rtol=1e-15)
     assert oracle.ns_sqrt(s, 16, -1.0, 1e-10, 10)["status"] == oracle.EINVAL
     assert oracle.ns_sqrt(s, 16, 1e-6, 0.0, 10)["status"] == oracle.EINVAL
+
+
+# ---------------------------------------------------------------------------
+# Damped map (Sec. 4.3): alpha(t), eps(t) driven by the trace error, switched
+# off once t_k < 0.1
+# ---------------------------------------------------------------------------
+
+def test_damped_map_switched_off_equals_plain_map():
+    """s' close to I (t_0 < 0.1 throughout): the damped run must be the plain
+    run bit for bit (the switched-off map is the plain map)."""
+    s = inputs.kms(256, 0.03)
+    plain = oracle.ns_sqrt(s, 32, 1e-8, 1e-12, 30, stagnation_stop=True)
+    assert plain["t"][0] < 0.1
+    damped = oracle.ns_sqrt(s, 32, 1e-8, 1e-12, 30, stagnation_stop=True, damped=True)
+    assert damped["iterations"] == plain["iterations"] and damped["status"] == plain["status"]
+    np.testing.assert_array_equal(damped["Y"], plain["Y"])
+    np.testing.assert_array_equal(damped["r"], plain["r"])
+
+
+def scalar_damped_ns(d, tol, maxit):
+    """The damped map on a diagonal s' = diag(d): every eigenvalue follows
+    y' = h y, z' = z h with the common alpha(t), eps(t) of the trace error
+    t = mean(1 - y z); alpha = 1, eps = 0 once t < 0.1."""
+    y, z = d.copy(), np.ones_like(d)
+    rs = []
+    for k in range(maxit + 1):
+        x = y * z
+        r = np.sqrt(np.sum((1.0 - x) ** 2))
+        rs.append(r)
+        if r < tol or k == maxit:
+            break
+        t = np.mean(1.0 - x)
+        if t >= 0.1:
+            a = 1.0 + 1.85 / (1.0 + np.exp(-50.0 * (t - 0.35)))
+            e = 0.1 / (1.0 + np.exp(-75.0 * (t - 0.30)))
+            h = np.sqrt(a) / 2.0 * (3.0 - a * (e + (1.0 - 2.0 * e) * x))
+        else:
+            h = 1.5 - 0.5 * x
+        y, z = h * y, z * h
+    return np.array(rs), y, z
+
+
+def test_damped_map_on_a_diagonal_is_the_scalar_map():
+    """A diagonal s reduces the matrix iteration to the scalar map on each
+    eigenvalue (padding, the trace error over the logical block, eps entering
+    on the diagonal only); tau = 0 keeps every block."""
+    d = np.exp(np.random.default_rng(3).uniform(np.log(1e-4), 0.0, 200))
+    d[0] = 1.0  # Gershgorin scale c = 1: s' = s
+    res = oracle.ns_sqrt(np.diag(d), 16, 0.0, 1e-10, 60, damped=True)
+    rs, y, z = scalar_damped_ns(d, 1e-10, 60)
+    assert res["status"] == oracle.OK and res["iterations"] == len(rs) - 1
+    np.testing.assert_allclose(res["r"], rs, rtol=1e-9, atol=1e-13)
+    np.testing.assert_allclose(np.diag(res["Y"]), y, rtol=1e-12)
+    np.testing.assert_allclose(np.diag(res["Z"]), z, rtol=1e-12)
+    off = res["Y"] - np.diag(np.diag(res["Y"]))
+    assert np.all(off == 0.0)
+
+
+def test_damped_map_converges_to_the_root_in_fewer_updates():
+    """Ill-conditioned Gramian (kappa ~ 8e5) at tau = 0: the damped map must
+    still converge to s^{1/2}, s^{-1/2} (its maps are off at the fixed point),
+    and the scaling must save updates over the plain map."""
+    s = inputs.gauss_gramian(8, 0.8)
+    plain = oracle.ns_sqrt(s, 32, 0.0, 1e-10, 60)
+    damped = oracle.ns_sqrt(s, 32, 0.0, 1e-10, 60, damped=True)
+    assert plain["status"] == oracle.OK and damped["status"] == oracle.OK
+    assert damped["iterations"] <= plain["iterations"] - 4
+    Yr, Zr = eig_sqrt(s)
+    assert rel(damped["Y"], Yr) < 1e-9 and rel(damped["Z"], Zr) < 1e-8
