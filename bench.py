@@ -34,23 +34,31 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--tau", type=float, default=1e-8)
+    p.add_argument("--tau", type=float, default=None)
     p.add_argument("--tau-s", type=float, default=-1.0)
     p.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3"])
-    p.add_argument("--tol", type=float, default=1e-10)
+    p.add_argument("--tol", type=float, default=None)
     p.add_argument("--maxit", type=int, default=40)
     p.add_argument("--literal-stop", action="store_true", help="disable the stagnation stop")
+    p.add_argument("--damped", action="store_true", help="the damped map (alpha(t), eps(t) of the trace error)")
     p.add_argument("--cpu-sample-iters", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--dump-launches", default=None, help="write per-launch (flops, ms) of the timed steps")
-    p.add_argument("--workload", default="gauss4096", choices=["gauss4096", "batched", "serving"],
+    p.add_argument("--compare-f64", action="store_true", help="also solve in FP64 and report the relative gap")
+    p.add_argument("--workload", default="gauss4096", choices=["gauss4096", "c3", "batched", "serving"],
                    help="gauss4096: the n=4096 Gaussian Gramian (default); batched: 64 uneven solves "
                         "together; serving: a Poisson request stream through the continuous-batching server")
     p.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     p.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     p.add_argument("--nmax", type=int, default=16384, help="serving: largest n (log-uniform from 512)")
     p.add_argument("--iters-per-step", type=int, default=4, help="batched: iterations per synchronisation")
-    return p.parse_args()
+    a = p.parse_args()
+    a.tau_cli, a.tol_cli = a.tau, a.tol
+    if a.tau is None:
+        a.tau = 1e-8
+    if a.tol is None:
+        a.tol = 1e-10
+    return a
 
 
 def run_batched(args):
@@ -239,6 +247,43 @@ def run_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_baseline_sampled_tiles(s, mu_rel, leaf, tau, info):
+    """The oracle on a bounded sample of a problem too large for it whole: the
+    pyramid of the regularised, scaled operand s' (all of it) and a sample of
+    output tiles of the first product s' (x)_tau s', timed and scaled to the
+    solve by retained triples (pyramid time counted once per product)."""
+    import oracle
+    import torch
+    c0 = float(s.abs().sum(1).max())
+    sm = s.clone()
+    sm.diagonal().add_(mu_rel * c0)
+    sm /= float(sm.abs().sum(1).max())
+    a = sm.cpu().numpy()
+    del sm
+    nb = -(-a.shape[0] // leaf)
+    rng = np.random.default_rng(0)
+    # output tiles on and near the diagonal, where the retained triples are
+    tiles = [(int(i), int(min(nb - 1, max(0, i + d)))) for i, d in
+             zip(rng.integers(0, nb, 48), rng.integers(-6, 7, 48))]
+    tc = time.perf_counter()
+    oracle.norms(a, leaf)
+    t_pyr = time.perf_counter() - tc
+    tc = time.perf_counter()
+    oracle.spamm_tiles(a, a, leaf, tau, [])   # set-up alone: copies and both pyramids
+    t_setup = time.perf_counter() - tc
+    tc = time.perf_counter()
+    _, counts = oracle.spamm_tiles(a, a, leaf, tau, tiles)
+    t_tiles = max(time.perf_counter() - tc - t_setup, 1e-9)
+    sample = int(np.sum(counts))
+    products = 3 * info["iterations"] + 1
+    sec = t_pyr * products + t_tiles * info["triples_total"] / max(sample, 1)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / sec, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"pyramid of s' ({t_pyr:.1f} s, counted once per product x {products}) + {len(tiles)} "
+                       f"output tiles of s' (x) s' near the diagonal ({sample} triples, {t_tiles:.2f} s net of "
+                       f"set-up) scaled to the solve's {info['triples_total']} triples")}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -256,19 +301,33 @@ def main():
 
     from paper_1508_05856_amd import inputs, spamm
 
-    cfg = inputs.config_c2(args.tau)
-    s_host = cfg["s"]
-    n, leaf = s_host.shape[0], cfg["leaf"]
-    stag = not args.literal_stop
     dev = torch.device("cuda:0")
-    s = torch.from_numpy(s_host).to(dev)
+    stag = not args.literal_stop
+    mu_rel = 0.0
+    if args.workload == "c3":
+        # n = 32768 ill-conditioned Gramian, built on the device (8 GiB in FP64)
+        cfg = inputs.config_c3_spec()
+        n, leaf = cfg["n"], cfg["leaf"]
+        s_host = None
+        s = inputs.gramian_device(inputs.gauss_positions(cfg["m"], cfg["h"], 0.1, 0, n), dev)
+        mu_rel = cfg["mu_rel"]
+        if args.tau_cli is None:
+            args.tau = cfg["tau"]
+        if args.tol_cli is None:
+            args.tol = cfg["tol"]
+    else:
+        cfg = inputs.config_c2(args.tau)
+        s_host = cfg["s"]
+        n, leaf = s_host.shape[0], cfg["leaf"]
+        s = torch.from_numpy(s_host).to(dev)
     Y = torch.empty_like(s)
     Z = torch.empty_like(s)
     ctx = spamm.Context(0)
 
-    def step():
-        return ctx.ns_sqrt(s, args.tau, args.tol, args.maxit, leaf=leaf, prec=args.prec, tau_s=args.tau_s,
-                           stagnation_stop=stag, Y=Y, Z=Z, raise_on_error=False)
+    def step(prec=args.prec, Yo=Y, Zo=Z):
+        return ctx.ns_sqrt(s, args.tau, args.tol, args.maxit, leaf=leaf, prec=prec, tau_s=args.tau_s,
+                           mu_rel=mu_rel, stagnation_stop=stag, damped=args.damped, Y=Yo, Z=Zo,
+                           raise_on_error=False)
 
     for _ in range(args.warmup):
         step()
@@ -306,6 +365,14 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     info = infos[-1]
 
+    rel_vs_f64 = None
+    if args.compare_f64 and args.prec != "f64":
+        Y64, Z64 = torch.empty_like(s), torch.empty_like(s)
+        step("f64", Y64, Z64)
+        rel_vs_f64 = dict(Y=float(torch.linalg.norm(Y - Y64) / torch.linalg.norm(Y64)),
+                          Z=float(torch.linalg.norm(Z - Z64) / torch.linalg.norm(Z64)))
+        del Y64, Z64
+
     # exact ||I - Y Z||_F with a dense FP64 product through the library (tau = 0)
     C, _, _ = ctx.spamm_multiply(Y, Z, 0.0, leaf)
     C.diagonal().sub_(1.0)
@@ -337,10 +404,11 @@ def main():
             "workload": cfg["name"], "n": n, "leaf": leaf, "tau": args.tau,
             "tau_s": args.tau if args.tau_s < 0 else args.tau_s, "tol": args.tol, "maxit": args.maxit,
             "stop": "literal" if not stag else "stagnation", "precision": args.prec,
+            "map": "damped" if args.damped else "plain",
             "status": spamm.STATUS_NAMES.get(info["status"], info["status"]),
             "iterations": info["iterations"], "resid_inloop": info["resid"], "resid_exact": resid_exact,
             "trace_err": info["trace_err"], "triples_per_solve": info["triples_total"],
-            "flops_per_solve": info["flops_total"],
+            "flops_per_solve": info["flops_total"], "mu_rel": mu_rel, "rel_vs_f64": rel_vs_f64,
         },
         "roofline": {
             "bound": "mfma", "kernel": "k_leaf_gemm_bf3" if args.prec == "bf16x3" else "k_leaf_gemm", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -351,7 +419,9 @@ def main():
         },
     }
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and s_host is None:
+        line["cpu_baseline"] = cpu_baseline_sampled_tiles(s, mu_rel, leaf, args.tau, info)
+    elif not args.no_cpu_baseline:
         import oracle
         m = args.cpu_sample_iters
         tc = time.perf_counter()

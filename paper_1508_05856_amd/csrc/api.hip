@@ -92,6 +92,7 @@ struct ProfRec {
 struct Plan {
     std::vector<unsigned long long> ids;
     int prec = 0, leaf = 0;
+    bool damped = false;  // some solve of the set uses the damped map
     char *mem = nullptr;
     size_t cap = 0;
     ProdTable tx{}, tyz{};
@@ -128,7 +129,7 @@ struct spamm_solve {
     Geom g;
     int prec;
     double tau, tau_s, tol, mu, c;
-    int maxit, stagnation;
+    int maxit, stagnation, damped;
     char *mem;
     size_t bytes;
     void *y[2], *z[2], *h;
@@ -298,6 +299,7 @@ ProdDesc x_product(const spamm_solve *s) {
     d.cnt = s->cnt[0];
     d.kidx = s->kidx[0];
     d.part = s->part;
+    d.fused_map = s->damped ? 0 : 1;
     d.state = s->state;
     return d;
 }
@@ -347,6 +349,7 @@ SolveDesc solve_desc(const spamm_solve *s) {
     d.nb = s->g.nb;
     d.maxit = s->maxit;
     d.stagnation_stop = s->stagnation;
+    d.damped = s->damped;
     d.tol = s->tol;
     d.part = s->part;
     d.cnt_x = s->cnt[0];
@@ -408,6 +411,7 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
     p->prec = group[0]->prec;
     p->leaf = group[0]->g.b;
     p->nsolve = (int)group.size();
+    p->damped = std::any_of(group.begin(), group.end(), [](const spamm_solve *s) { return s->damped != 0; });
     p->cap = sizing.off;
     hipError_t e = hipMalloc((void **)&p->mem, p->cap);
     if (e == hipSuccess)
@@ -451,6 +455,7 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
     HIPCHK(launch_plan_tab(p->tx, p->leaf, (int)elt_size(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
     HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
+    if (p->damped) HIPCHK(launch_ns_map(kp, p->tx, p->leaf, st));
     TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
     TIMED(K_CULL, launch_cull_tab(p->tyz, st));
     HIPCHK(launch_plan_tab(p->tyz, p->leaf, (int)elt_size(p->prec), st));
@@ -552,6 +557,7 @@ spamm_ns_opts default_opts(const spamm_ns_opts *opts) {
     o.tau_s = -1.0;
     o.mu_rel = 0.0;
     o.stagnation_stop = 0;
+    o.damped = 0;
     if (opts) {
         o = *opts;
         if (o.leaf == 0) o.leaf = 32;
@@ -797,6 +803,7 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
     sv->c = c;
     sv->maxit = maxit;
     sv->stagnation = o.stagnation_stop ? 1 : 0;
+    sv->damped = o.damped ? 1 : 0;
     sv->mem = nullptr;
     sv->bytes = solve_bytes(g, o.prec, maxit, nullptr);
     hipError_t e = hipMalloc((void **)&sv->mem, sv->bytes);
@@ -822,6 +829,7 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
     chk(launch_pyramid(g, sv->qy[0], sv->ny[0], sv->qz[0], sv->nz[0], 2, st), "pyramid");
     SolveState init{};
     init.status = ST_RUNNING;
+    init.alpha = 1.0;
     sv->host_state = init;
     chk(hipMemcpyAsync(sv->state, &sv->host_state, sizeof(SolveState), hipMemcpyHostToDevice, st), "state");
     chk(hipStreamSynchronize(st), "synchronise");

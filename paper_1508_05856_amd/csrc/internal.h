@@ -41,8 +41,9 @@ struct SolveState {
     int status;       // ST_RUNNING, or the final spamm_status
     int k;            // index of the current iterate (updates performed so far)
     int parity;       // y/z buffer holding the current iterate
-    int nondecrease;  // consecutive r_k >= 0.99 r_{k-1}
-    double r0, r_prev, r, t;
+    int nondecrease;  // consecutive r_k >= 0.99 r_best with r_best < 1/2
+    double r0, r_prev, r, t;  // r_prev: the best (smallest) residual so far
+    double alpha, eps;        // damped map of the next update (1, 0 when undamped or switched off)
     int64_t triples;  // retained triples of all products so far
 };
 
@@ -51,6 +52,7 @@ struct SolveDesc {
     int64_t n;
     int nb;
     int maxit, stagnation_stop;
+    int damped;          // the map's alpha(t), eps(t) are set from t_k (else alpha = 1, eps = 0)
     double tol;
     const double *part;  // nb*nb*2: per-tile (sum (I-x)^2, trace x) of the x product
     const int32_t *cnt_x, *cnt_y, *cnt_z;
@@ -77,7 +79,9 @@ struct ProdDesc {
     double *nrmC[2];                    // C's leaf norms (written by the pyramid pass)
     int32_t *cnt;                       // nb*nb retained counts
     int32_t *kidx;                      // nb*nb*nb retained k lists
-    double *part;                       // non-null: Newton-Schulz x product (writes h and partials)
+    double *part;                       // non-null: Newton-Schulz x product (writes per-tile partials)
+    int fused_map;                      // x product: the epilogue writes h = 1.5 I - 0.5 x (else x itself,
+                                        // mapped afterwards by the damped-map pass)
     const SolveState *state;            // null: always runs, parity 0
 };
 
@@ -94,6 +98,7 @@ struct Job {
     const int32_t *list;  // retained k, increasing
     int64_t n;            // logical order
     int nb, cnt, i, j;
+    int fused_map;        // with part: write h = 1.5 I - 0.5 x instead of x
     int k0, k1;           // list[0], list[1] when present (the first stages need no list load)
 };
 
@@ -143,6 +148,9 @@ hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t s
 hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st);  // pyramid of each product's C
 // Per solve: r_k, t_k, |R| records and the stop decision.
 hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, hipStream_t st);
+// Damped map of every damped running solve's x product, in place:
+// h = (sqrt(alpha)/2) (3 I - alpha (eps I + (1 - 2 eps) x)), and h's leaf norms.
+hipError_t launch_ns_map(int prec, const ProdTable &t, int leaf, hipStream_t st);
 // After a (y, z) update: parity ^= 1, k += 1 for running solves.
 hipError_t launch_ns_advance(const SolveDesc *solves, int nsolve, hipStream_t st);
 // Copy each solve's state into a contiguous array (for one read-back).

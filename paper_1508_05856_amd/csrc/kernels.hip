@@ -465,6 +465,7 @@ __device__ inline Job make_job(const ProdDesc &d, int t, int cnt, int b, int esz
     J.cnt = cnt;
     J.i = i;
     J.j = j;
+    J.fused_map = d.fused_map;
     J.k0 = cnt > 0 ? J.list[0] : 0;
     J.k1 = cnt > 1 ? J.list[1] : 0;
     return J;
@@ -802,7 +803,7 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(const Job *_
                     const double ex = (diag ? 1.0 : 0.0) - x;
                     if (logical) r2 += ex * ex;
                     if (diag) tr += x;
-                    out = (T)h;
+                    out = J.fused_map ? (T)h : (T)x;
                 } else {
                     out = (T)x;
                 }
@@ -1022,7 +1023,7 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
                     const double ex = (diag ? 1.0 : 0.0) - x;
                     if (logical) r2 += ex * ex;
                     if (diag) tr += x;
-                    out = (float)h;
+                    out = J.fused_map ? (float)h : (float)x;
                 } else {
                     out = (float)x;
                 }
@@ -1093,7 +1094,8 @@ hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t s
 // (I-x)^2), t_k = (n - trace)/n and the retained-triple counts, summed in a
 // fixed order, then the stop tests in the order: r_k < tol (OK); r_k not
 // finite or > 10 max(r_0, sqrt(n)) (diverged); two consecutive
-// r_k >= 0.99 r_{k-1} (stagnated, opt-in); k == maxit (not converged).
+// r_k >= 0.99 r_best with r_best = min(r_0..r_{k-1}) < 1/2 (stagnated,
+// opt-in); k == maxit (not converged).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict__ solves) {
     __shared__ double sh[16];
@@ -1138,15 +1140,72 @@ __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict_
         status = -3;  // SPAMM_EDIVERGED
     } else {
         if (sd.stagnation_stop && k > 0) {
-            st->nondecrease = (r >= 0.99 * st->r_prev) ? st->nondecrease + 1 : 0;
+            // progress against the best residual so far, counted only below
+            // 1/2: there an exact update shrinks r by more than 2x, so a step
+            // gaining under 1% is the floor
+            st->nondecrease = (st->r_prev < 0.5 && r >= 0.99 * st->r_prev) ? st->nondecrease + 1 : 0;
             if (st->nondecrease >= 2) status = 2;  // SPAMM_STAGNATED
         }
         if (status == ST_RUNNING) {
-            st->r_prev = r;
+            if (k == 0 || r < st->r_prev) st->r_prev = r;  // best residual so far
             if (k == sd.maxit) status = 1;  // SPAMM_NOT_CONVERGED
         }
     }
+    // damped map (Sec. 4.3): scaling alpha(t) and stabilisation eps(t) of the
+    // trace error, both switched off once t_k < 0.1 (the sigmoids never reach
+    // 1 and 0 exactly; eps(0) alone would hold r above sqrt(n) 1.7e-11)
+    double alpha = 1.0, eps = 0.0;
+    if (sd.damped && tk >= 0.1) {
+        alpha = 1.0 + 1.85 / (1.0 + exp(-50.0 * (tk - 0.35)));
+        eps = 0.1 / (1.0 + exp(-75.0 * (tk - 0.30)));
+    }
+    st->alpha = alpha;
+    st->eps = eps;
     st->status = status;
+}
+
+// Damped map, one workgroup per tile of the x products of a table, in place.
+// An off-diagonal tile with no retained triple holds exact zeros and maps to
+// zeros (its squared norm, 0, is already written), so it is skipped.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns_map(const ProdDesc *__restrict__ prods, const int32_t *__restrict__ pre,
+                                                int nprod, int b) {
+    __shared__ double sh[4];
+    const int g = blockIdx.x;
+    const int p = find_slot(pre, nprod, g);
+    const ProdDesc &d = prods[p];
+    if (d.part == nullptr || d.fused_map || !prod_running(d)) return;
+    const int par = prod_parity(d);
+    const int nb = d.nb, t = g - pre[p], i = t / nb, j = t % nb;
+    if (i != j && d.cnt[t] == 0) return;
+    const double alpha = d.state->alpha, eps = d.state->eps;
+    const bool plain = (alpha == 1.0 && eps == 0.0);
+    const double hs = 0.5 * sqrt(alpha), om = 1.0 - 2.0 * eps;
+    T *tile = (T *)d.C[par] + (int64_t)t * b * b;
+    double q = 0.0;
+    for (int e = threadIdx.x; e < b * b; e += 256) {
+        const int r = e / b, c = e % b;
+        const int64_t gi = (int64_t)i * b + r, gj = (int64_t)j * b + c;
+        const bool diag = (gi == gj) && (gi < d.n);
+        const double x = (double)tile[e];
+        const double h = plain ? (diag ? 1.5 : 0.0) - 0.5 * x
+                               : hs * ((diag ? 3.0 : 0.0) - alpha * ((diag ? eps : 0.0) + om * x));
+        const T out = (T)h;
+        tile[e] = out;
+        q += (double)out * (double)out;
+    }
+    q = block_sum<256>(q, sh);
+    if (threadIdx.x == 0) d.qC[par][(int64_t)i * d.P + j] = q;
+}
+
+hipError_t launch_ns_map(int prec, const ProdTable &t, int leaf, hipStream_t st) {
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_ns_map<double>, dim3(t.total_tiles), dim3(256), 0, st, t.prods, t.tile_pre, t.nprod,
+                           leaf);
+    else
+        hipLaunchKernelGGL(k_ns_map<float>, dim3(t.total_tiles), dim3(256), 0, st, t.prods, t.tile_pre, t.nprod,
+                           leaf);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(64) void k_ns_advance(const SolveDesc *__restrict__ solves, int nsolve) {

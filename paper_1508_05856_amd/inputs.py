@@ -141,6 +141,12 @@ def config_c3(m: int = 32) -> dict:
                 tau=1e-6, tol=1e-8, maxit=40, mu_rel=1e-4)
 
 
+def config_c3_spec(m: int = 32) -> dict:
+    """The C3 parameters without materialising s (n = m^3 = 32768 is 8 GiB in FP64)."""
+    return dict(name=f"gauss_m{m}_h0.6_mu1e-4_b64", m=m, n=m ** 3, h=0.6, leaf=64, tau=1e-6, tol=1e-8,
+                maxit=40, mu_rel=1e-4)
+
+
 def batch_specs(count: int = 64, seed: int = 0, nmin_blocks: int = 4, nmax_blocks: int = 64) -> list[dict]:
     """Batched workload: n = 64*U{4..64}; half KMS (rho ~ U[0.5,0.9]), half Gaussian
     (h ~ U[0.8,1.2], first n Morton sites of the smallest cube); tau in {1e-4, 1e-6}."""

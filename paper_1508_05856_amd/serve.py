@@ -33,6 +33,7 @@ class Request:
     tau_s: float = -1.0
     mu_rel: float = 0.0
     stagnation_stop: bool = True
+    damped: bool = False
     t_submit: float = 0.0
     future: Future = field(default_factory=Future)
     footprint: int = 0
@@ -119,7 +120,7 @@ class Server:
             try:
                 sv = self.ctx.solve_begin(req.s, req.tau, req.tol, req.maxit, leaf=req.leaf, prec=req.prec,
                                           tau_s=req.tau_s, mu_rel=req.mu_rel,
-                                          stagnation_stop=req.stagnation_stop)
+                                          stagnation_stop=req.stagnation_stop, damped=req.damped)
             except Exception as e:  # invalid input or no memory: fail this request only
                 req.s = None
                 req.future.set_exception(e)

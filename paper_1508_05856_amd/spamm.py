@@ -45,7 +45,7 @@ class Stats(ctypes.Structure):
 
 class NsOpts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("prec", ctypes.c_int), ("tau_s", ctypes.c_double),
-                ("mu_rel", ctypes.c_double), ("stagnation_stop", ctypes.c_int)]
+                ("mu_rel", ctypes.c_double), ("stagnation_stop", ctypes.c_int), ("damped", ctypes.c_int)]
 
 
 class NsResult(ctypes.Structure):
@@ -186,7 +186,7 @@ class Context:
         return C, stats, trip
 
     def ns_sqrt(self, s: torch.Tensor, tau: float, tol: float, maxit: int, leaf: int = 32, prec="f64",
-                tau_s: float = -1.0, mu_rel: float = 0.0, stagnation_stop: bool = False,
+                tau_s: float = -1.0, mu_rel: float = 0.0, stagnation_stop: bool = False, damped: bool = False,
                 Y: torch.Tensor | None = None, Z: torch.Tensor | None = None, raise_on_error: bool = True):
         """Y ~ s^{1/2}, Z ~ s^{-1/2}.  Returns (Y, Z, info dict)."""
         ps, ld = _mat(s, "s")
@@ -198,7 +198,7 @@ class Context:
         if ldy != ld or ldz != ld:
             raise ValueError("Y and Z must share s's leading dimension")
         opts = NsOpts(leaf, _PREC[prec] if isinstance(prec, str) else int(prec), float(tau_s), float(mu_rel),
-                      int(bool(stagnation_stop)))
+                      int(bool(stagnation_stop)), int(bool(damped)))
         res = NsResult()
         status = self.lib.ns_sqrt(self.handle, ps, py, pz, n, ld, float(tau), float(tol), int(maxit),
                                   ctypes.byref(opts), ctypes.byref(res), _stream_ptr(s.device))
@@ -216,10 +216,11 @@ class Context:
                                                   maxit))
 
     def solve_begin(self, s: torch.Tensor, tau: float, tol: float, maxit: int, leaf: int = 32, prec="f64",
-                    tau_s: float = -1.0, mu_rel: float = 0.0, stagnation_stop: bool = False) -> "Solve":
+                    tau_s: float = -1.0, mu_rel: float = 0.0, stagnation_stop: bool = False,
+                    damped: bool = False) -> "Solve":
         ps, ld = _mat(s, "s")
         opts = NsOpts(leaf, _PREC[prec] if isinstance(prec, str) else int(prec), float(tau_s), float(mu_rel),
-                      int(bool(stagnation_stop)))
+                      int(bool(stagnation_stop)), int(bool(damped)))
         h = ctypes.c_void_p()
         _check(self.lib.spamm_solve_begin(self.handle, ps, s.shape[0], ld, float(tau), float(tol), int(maxit),
                                           ctypes.byref(opts), ctypes.byref(h), _stream_ptr(s.device)))
