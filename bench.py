@@ -264,7 +264,7 @@ def cpu_baseline_sampled_tiles(s, mu_rel, leaf, tau, info):
     rng = np.random.default_rng(0)
     # output tiles on and near the diagonal, where the retained triples are
     tiles = [(int(i), int(min(nb - 1, max(0, i + d)))) for i, d in
-             zip(rng.integers(0, nb, 48), rng.integers(-6, 7, 48))]
+             zip(rng.integers(0, nb, 3000), rng.integers(-6, 7, 3000))]
     tc = time.perf_counter()
     oracle.norms(a, leaf)
     t_pyr = time.perf_counter() - tc
@@ -315,6 +315,9 @@ def main():
             args.tau = cfg["tau"]
         if args.tol_cli is None:
             args.tol = cfg["tol"]
+        if args.tau_s < 0:
+            args.tau_s = cfg["tau_s_rel"] * args.tau
+        args.damped = args.damped or cfg["damped"]
     else:
         cfg = inputs.config_c2(args.tau)
         s_host = cfg["s"]

@@ -119,9 +119,11 @@ typedef struct {
     double tau_s;        /* threshold of the y channel h (x) y; < 0 = tau (Sec. 4.1)         */
     double mu_rel;       /* Tikhonov shift s + mu_rel * c0 * I, c0 the Gershgorin bound of s
                             (Sec. 6); 0 = none                                             */
-    int stagnation_stop; /* 1 = stop when r_k >= 0.99 r_best, r_best = min(r_0..r_{k-1})
-                            < 1/2, twice in a row (below 1/2 an exact update shrinks r
-                            more than 2x, so no 1% gain means the tau/rounding floor)  */
+    int stagnation_stop; /* 1 = stop when r_k >= 0.99 r_best, r_best = min(r_0..r_{k-1}),
+                            twice in a row while r_best < 1/2 or n |t_k| < 1/2 (then every
+                            eigenvalue of an exact iterate is within 1/2 of 1, where an
+                            update shrinks r more than 2x: no 1% gain means the
+                            tau/rounding floor)                                         */
     int damped;          /* 1 = the damped map of Sec. 4.3 "Mapping": h = (sqrt(a)/2)
                             (3 I - a xs), xs = e I + (1 - 2e) x, with the scaling
                             a(t) = 1 + 1.85/(1 + exp(-50 (t - 0.35))) and stabilisation
@@ -147,8 +149,8 @@ typedef struct {
  * z_0 = I_n.  For k = 0, 1, ...: x_k = y_k (x)_tau z_k; r_k = ||I_n - x_k||_F;
  * stop with OK when r_k < tol, EDIVERGED when r_k is not finite or exceeds
  * 10 max(r_0, sqrt(n)), STAGNATED (opt-in) after two consecutive
- * r_k >= 0.99 r_best (r_best = min(r_0..r_{k-1}) < 1/2), NOT_CONVERGED when
- * k == maxit; otherwise
+ * r_k >= 0.99 r_best (r_best = min(r_0..r_{k-1})) while r_best < 1/2 or
+ * n |t_k| < 1/2, NOT_CONVERGED when k == maxit; otherwise
  * h_k = 1.5 I_n - 0.5 x_k, y_{k+1} = h_k (x)_{tau_s} y_k, z_{k+1} = z_k (x)_tau h_k.
  *
  * s: DEVICE input, symmetric (max|s - s^T| <= 1e-14 max|s|) and finite, else

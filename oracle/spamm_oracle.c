@@ -458,15 +458,17 @@ int oracle_ns_step(const double *y_in, const double *z_in, double *y_out, double
  *     r_k < tol                       -> OK, return (y_k, z_k)
  *     r_k not finite or
  *       r_k > 10 max(r_0, sqrt(n))    -> DIVERGED
- *     stagnation_stop and, on two consecutive k, r_best < 1/2 and
- *       r_k >= .99 r_best, r_best = min(r_0 .. r_{k-1})
+ *     stagnation_stop and, on two consecutive k, r_k >= .99 r_best with
+ *       r_best = min(r_0 .. r_{k-1}), while r_best < 1/2 or |t_k| < 1/(2n)
  *                                     -> STAGNATED (outputs valid)
- *       (with r < 1/2 every eigenvalue x of x has |1 - x| < 1/2, where one
- *       exact update maps 1 - x to (1 - x)^2 (2 + x)/4, at most 0.44 (1 - x):
- *       two updates that fail to gain 1% on the best residual are the
- *       tau/rounding floor, not the slow start of an ill-conditioned
- *       iteration; the best, not the previous, residual keeps a fluctuating
- *       floor from resetting the count)
+ *       (either guard means every eigenvalue x of an exact iterate has
+ *       |1 - x| < 1/2: r bounds the largest |1 - x|, and exact iterates keep
+ *       x in (0, 1], so n t_k bounds it too.  There one exact update maps
+ *       1 - x to (1 - x)^2 (2 + x)/4, at most 0.44 (1 - x): two updates that
+ *       fail to gain 1% on the best residual are the tau/rounding floor, not
+ *       the slow start of an ill-conditioned iteration.  The best, not the
+ *       previous, residual keeps a fluctuating floor from resetting the
+ *       count.)
  *     k == maxit                      -> NOT_CONVERGED (outputs valid)
  *     h_k = (3 I_n - x_k)/2, or with damping the map of damping() and
  *       ns_update() at alpha(t_k), eps(t_k);
@@ -534,7 +536,8 @@ int oracle_ns_sqrt(const double *s, double *Y, double *Z, int64_t n, int64_t b, 
         if (r < tol) { status = ORC_OK; break; }
         if (!isfinite(r) || r > 10.0 * fmax(r0, sqrt((double)n))) { status = ORC_EDIVERGED; break; }
         if (stagnation_stop && k > 0) {
-            nondecrease = (r_best < 0.5 && r >= 0.99 * r_best) ? nondecrease + 1 : 0;
+            const int settled = r_best < 0.5 || fabs(t) * (double)n < 0.5;
+            nondecrease = (settled && r >= 0.99 * r_best) ? nondecrease + 1 : 0;
             if (nondecrease >= 2) { status = ORC_STAGNATED; break; }
         }
         if (k == 0 || r < r_best) r_best = r;

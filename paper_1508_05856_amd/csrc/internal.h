@@ -41,7 +41,7 @@ struct SolveState {
     int status;       // ST_RUNNING, or the final spamm_status
     int k;            // index of the current iterate (updates performed so far)
     int parity;       // y/z buffer holding the current iterate
-    int nondecrease;  // consecutive r_k >= 0.99 r_best with r_best < 1/2
+    int nondecrease;  // consecutive r_k >= 0.99 r_best while r_best < 1/2 or n |t_k| < 1/2
     double r0, r_prev, r, t;  // r_prev: the best (smallest) residual so far
     double alpha, eps;        // damped map of the next update (1, 0 when undamped or switched off)
     int64_t triples;  // retained triples of all products so far

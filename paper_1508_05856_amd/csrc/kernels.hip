@@ -1094,8 +1094,8 @@ hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t s
 // (I-x)^2), t_k = (n - trace)/n and the retained-triple counts, summed in a
 // fixed order, then the stop tests in the order: r_k < tol (OK); r_k not
 // finite or > 10 max(r_0, sqrt(n)) (diverged); two consecutive
-// r_k >= 0.99 r_best with r_best = min(r_0..r_{k-1}) < 1/2 (stagnated,
-// opt-in); k == maxit (not converged).
+// r_k >= 0.99 r_best, r_best = min(r_0..r_{k-1}), while r_best < 1/2 or
+// n |t_k| < 1/2 (stagnated, opt-in); k == maxit (not converged).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict__ solves) {
     __shared__ double sh[16];
@@ -1140,10 +1140,13 @@ __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict_
         status = -3;  // SPAMM_EDIVERGED
     } else {
         if (sd.stagnation_stop && k > 0) {
-            // progress against the best residual so far, counted only below
-            // 1/2: there an exact update shrinks r by more than 2x, so a step
-            // gaining under 1% is the floor
-            st->nondecrease = (st->r_prev < 0.5 && r >= 0.99 * st->r_prev) ? st->nondecrease + 1 : 0;
+            // progress against the best residual so far, counted only once
+            // every eigenvalue of an exact iterate is within 1/2 of 1 (best r
+            // below 1/2, or n |t_k| below 1/2 since exact iterates keep x in
+            // (0, 1]): there an exact update shrinks r by more than 2x, so a
+            // step gaining under 1% is the floor
+            const bool settled = st->r_prev < 0.5 || fabs(tk) * (double)sd.n < 0.5;
+            st->nondecrease = (settled && r >= 0.99 * st->r_prev) ? st->nondecrease + 1 : 0;
             if (st->nondecrease >= 2) status = 2;  // SPAMM_STAGNATED
         }
         if (status == ST_RUNNING) {

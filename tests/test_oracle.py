@@ -415,6 +415,23 @@ def test_stagnation_stop_ignores_the_slow_start():
     np.testing.assert_allclose(np.diag(res["Y"]), np.sqrt(d), rtol=1e-12)
 
 
+def test_stagnation_stop_on_a_high_floor_through_the_trace_guard():
+    """A coarse tau leaves a floor with r well above 1/2 (KMS 0.9, n = 512,
+    tau = 1e-2: r ~ 4.9) while n |t_k| < 1/2 shows every eigenvalue settled:
+    the rule must stop there instead of running to maxit, and must not have
+    counted any step before n |t_k| < 1/2."""
+    s = inputs.kms(512, 0.9)
+    res = oracle.ns_sqrt(s, 32, 1e-2, 1e-10, 40, stagnation_stop=True)
+    k = res["iterations"]
+    assert res["status"] == oracle.STAGNATED and k < 20
+    r, t = res["r"][:k + 1], res["t"][:k + 1]
+    assert r.min() > 0.5                                   # the residual guard never held
+    assert np.all(np.abs(t[-2:]) * 512 < 0.5) and np.all(r[-2:] >= 0.99 * r[:-2].min())
+    lit = oracle.ns_sqrt(s, 32, 1e-2, 1e-10, 40)
+    np.testing.assert_array_equal(lit["r"][:k + 1], r)      # same path until the stop
+    assert lit["status"] == oracle.NOT_CONVERGED
+
+
 def test_ns_status_codes():
     s = inputs.kms(64, 0.6)
     bad = s.copy()
