@@ -45,7 +45,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--dump-launches", default=None, help="write per-launch (flops, ms) of the timed steps")
     p.add_argument("--compare-f64", action="store_true", help="also solve in FP64 and report the relative gap")
-    p.add_argument("--workload", default="gauss4096", choices=["gauss4096", "c3", "batched", "serving"],
+    p.add_argument("--copy-bytes", type=int, default=1 << 31, help="copy: bytes read (and written) per launch")
+    p.add_argument("--workload", default="gauss4096", choices=["gauss4096", "c3", "batched", "serving", "copy"],
                    help="gauss4096: the n=4096 Gaussian Gramian (default); batched: 64 uneven solves "
                         "together; serving: a Poisson request stream through the continuous-batching server")
     p.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -284,6 +285,28 @@ def cpu_baseline_sampled_tiles(s, mu_rel, leaf, tau, info):
                        f"set-up) scaled to the solve's {info['triples_total']} triples")}
 
 
+def run_copy(args):
+    """A plain elementwise device copy of known size (y = -x over FP64), the
+    reference that scales hardware read/write byte counters to bytes."""
+    import torch
+    n = args.copy_bytes // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": "device copy bandwidth (read + write)", "value": 2 * n * 8 / dt / 1e9,
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": dt * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "copy", "bytes_read_per_launch": n * 8,
+                                 "bytes_written_per_launch": n * 8}}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -295,6 +318,9 @@ def main():
         return
     if args.workload == "serving":
         run_serving(args)
+        return
+    if args.workload == "copy":
+        run_copy(args)
         return
 
     import torch

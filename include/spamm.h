@@ -131,10 +131,15 @@ typedef struct {
                             t_k = (n - tr x_k)/n; both switched off (a = 1, e = 0) once
                             t_k < 0.1, so the fixed point stays x = I.  0 = the plain
                             map h = 1.5 I - 0.5 x                                       */
+    int single;          /* 1 = the single-channel instance (Sec. 3.2, eq. "single"):
+                            z_0 = I_n; y_k = s' (x)_{tau_s} z_k (the y channel implicit in
+                            the product with s, taken rightmost at the tighter tau_s),
+                            x_k = z_k^T (x)_tau y_k, z_{k+1} = z_k (x)_tau h_k; Y = sqrt(c)
+                            y_k.  Same stop tests and map.  0 = dual channel            */
 } spamm_ns_opts;
 
 typedef struct {
-    int iterations;        /* (y, z) updates performed                                  */
+    int iterations;        /* updates performed                                         */
     double resid;          /* last in-loop r_k = ||I_n - y_k (x)_tau z_k||_F             */
     double trace_err;      /* last t_k = (n - tr x_k)/n (Sec. 4.2)                       */
     double scale;          /* c, the Gershgorin bound used to scale s                    */
@@ -163,7 +168,7 @@ int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, in
             double tol, int maxit, const spamm_ns_opts *opts, spamm_ns_result *res, void *stream);
 
 /*
- * Step API: the same dual-channel iteration as ns_sqrt, advanced explicitly so
+ * Step API: the same iteration as ns_sqrt, advanced explicitly so
  * that many solves share launches (batched solves of uneven n) and solves
  * can join and leave between steps (continuous batching for serving).
  * ns_sqrt is spamm_solve_begin + spamm_solve_step until done +
@@ -172,10 +177,12 @@ int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, in
 typedef struct spamm_solve spamm_solve;
 
 /* Device bytes one solve holds from begin to finish (for admission control):
- * five b x b-tiled iterates (y, y', z, z', h) in the leaf precision, five norm
- * pyramids, three task lists of ceil(n/b)^3 int32, per-tile partials and the
- * per-iteration records.  0 on bad arguments. */
-size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit);
+ * five b x b-tiled iterates (dual: y, y', z, z', h; single: s', y_k, z, z',
+ * h, and a sixth, z^T) in the leaf precision, as many norm pyramids, three
+ * task lists of ceil(n/b)^3 int32, per-tile partials and the per-iteration
+ * records.  single: 0 = dual channel, 1 = single channel.  0 on bad
+ * arguments. */
+size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit, int single);
 
 /* Checks s (as ns_sqrt), scales it, allocates the solve's device memory and
  * sets y_0 = s', z_0 = I_n.  s may be freed once this returns (synchronises).

@@ -56,10 +56,11 @@ def _load():
             lib.oracle_ns_step.argtypes = [dp, dp, dp, dp, i64, i64, ctypes.c_double, ctypes.c_double]
             lib.oracle_ns_sqrt.argtypes = [dp, dp, dp, i64, i64, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                           ctypes.c_int, dp, dp, lp, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.c_int, ctypes.c_int, dp, dp, lp, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_double)]
+            lib.oracle_ns_single_step.argtypes = [dp, dp, dp, dp, i64, i64, ctypes.c_double, ctypes.c_double]
             for f in (lib.oracle_norms, lib.oracle_spamm, lib.oracle_spamm_tiles, lib.oracle_ns_sqrt,
-                      lib.oracle_ns_step):
+                      lib.oracle_ns_step, lib.oracle_ns_single_step):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -144,10 +145,10 @@ def spamm_tiles(a, b, leaf: int, tau: float, tiles):
 
 
 def ns_sqrt(s, leaf: int, tau: float, tol: float, maxit: int, tau_s: float = -1.0, mu_rel: float = 0.0,
-            stagnation_stop: bool = False, damped: bool = False) -> dict:
-    """Dual-channel coupled Newton-Schulz (optionally with the damped map of
-    Sec. 4.3).  Returns a dict with Y, Z, status, iterations, scale and the r,
-    t and |R| histories."""
+            stagnation_stop: bool = False, damped: bool = False, single: bool = False) -> dict:
+    """Coupled Newton-Schulz, dual channel or (single=True) the single
+    channel instance, optionally with the damped map of Sec. 4.3.  Returns a
+    dict with Y, Z, status, iterations, scale and the r, t and |R| histories."""
     s = _f64(s)
     n = s.shape[0]
     lib = _load()
@@ -160,6 +161,7 @@ def ns_sqrt(s, leaf: int, tau: float, tol: float, maxit: int, tau_s: float = -1.
     sc = ctypes.c_double(0.0)
     st = lib.oracle_ns_sqrt(_dptr(s), _dptr(Y), _dptr(Z), n, leaf, float(tau), float(tau_s), float(tol),
                             int(maxit), float(mu_rel), int(bool(stagnation_stop)), int(bool(damped)),
+                            int(bool(single)),
                             _dptr(r), _dptr(t),
                             nr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(it),
                             ctypes.byref(sc))
@@ -179,3 +181,16 @@ def ns_step(y, z, leaf: int, tau: float, tau_s: float = -1.0):
     if st:
         raise OracleError(f"oracle_ns_step status {st}")
     return yo, zo
+
+
+def ns_single_step(s, z, leaf: int, tau: float, tau_s: float = -1.0):
+    """One single-channel step from any (s', z): returns (y, z_next) with
+    y = s' (x)_{tau_s} z and z_next = z (x)_tau h[z^T (x)_tau y] (plain map)."""
+    s, z = _f64(s), _f64(z)
+    n = s.shape[0]
+    y = np.zeros_like(s)
+    zn = np.zeros_like(s)
+    st = _load().oracle_ns_single_step(_dptr(s), _dptr(z), _dptr(y), _dptr(zn), n, leaf, float(tau), float(tau_s))
+    if st:
+        raise OracleError(f"oracle_ns_single_step status {st}")
+    return y, zn

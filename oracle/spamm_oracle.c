@@ -398,8 +398,7 @@ static void damping(int damped, double t, double *alpha, double *eps) {
  * Undamped (alpha = 1, eps = 0): h_k = 1.5 I_n - 0.5 x_k.  Damped: the
  * stabilising map [0,1] -> [eps, 1-eps], xs = eps I_n + (1 - 2 eps) x_k, then
  * the scaled logistic h_alpha[xs] = (sqrt(alpha)/2) (3 I_n - alpha xs). */
-static void ns_update(qmat *x, const qmat *y, const qmat *z, qmat *yn, qmat *zn, double tau, double tau_s,
-                      double alpha, double eps, int64_t *ny, int64_t *nz) {
+static void ns_map(qmat *x, double alpha, double eps) {
     const int64_t n = x->n, np = x->np;
     const int plain = (alpha == 1.0 && eps == 0.0);
     const double half_sqrt_alpha = 0.5 * sqrt(alpha);
@@ -415,7 +414,69 @@ static void ns_update(qmat *x, const qmat *y, const qmat *z, qmat *yn, qmat *zn,
             }
         }
     qmat_norms(x);
+}
+
+static void ns_update(qmat *x, const qmat *y, const qmat *z, qmat *yn, qmat *zn, double tau, double tau_s,
+                      double alpha, double eps, int64_t *ny, int64_t *nz) {
+    ns_map(x, alpha, eps);
     *ny = spamm(x, y, yn, tau_s, NULL, 0);
+    *nz = spamm(z, x, zn, tau, NULL, 0);
+}
+
+/* r_k = ||I_n - x||_F and t_k = (n - tr x)/n over the logical block. */
+static void resid_trace(const qmat *x, double *r, double *t) {
+    const int64_t n = x->n, np = x->np;
+    double r2 = 0.0, tr = 0.0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < n; j++) {
+            const double v = x->a[i * np + j];
+            const double e = (i == j ? 1.0 : 0.0) - v;
+            r2 += e * e;
+            if (i == j) tr += v;
+        }
+    *r = sqrt(r2);
+    *t = ((double)n - tr) / (double)n;
+}
+
+/* The stop tests of oracle_ns_sqrt, in their order; ORC_CONTINUE to go on. */
+#define ORC_CONTINUE 100
+typedef struct {
+    double r0, r_best;
+    int nondecrease;
+} stopper;
+
+static int stop_test(stopper *S, int k, double r, double t, int64_t n, double tol, int maxit, int stagnation_stop) {
+    if (k == 0) S->r0 = r;
+    if (r < tol) return ORC_OK;
+    if (!isfinite(r) || r > 10.0 * fmax(S->r0, sqrt((double)n))) return ORC_EDIVERGED;
+    if (stagnation_stop && k > 0) {
+        const int settled = S->r_best < 0.5 || fabs(t) * (double)n < 0.5;
+        S->nondecrease = (settled && r >= 0.99 * S->r_best) ? S->nondecrease + 1 : 0;
+        if (S->nondecrease >= 2) return ORC_STAGNATED;
+    }
+    if (k == 0 || r < S->r_best) S->r_best = r;
+    if (k == maxit) return ORC_NOT_CONVERGED;
+    return ORC_CONTINUE;
+}
+
+/* t = m^T (same geometry), norms rebuilt. */
+static void qmat_transpose(const qmat *m, qmat *t) {
+    const int64_t np = m->np;
+    for (int64_t i = 0; i < np; i++)
+        for (int64_t j = 0; j < np; j++) t->a[j * np + i] = m->a[i * np + j];
+    qmat_norms(t);
+}
+
+/* One single-channel step (Sec. 3.2, eq. "single") from s' and z:
+ * y = s' (x)_{tau_s} z (the implicit y channel: the product involving s,
+ * taken rightmost and at the tighter threshold), x = z^T (x)_tau y,
+ * h = h[x] at (alpha, eps), zn = z (x)_tau h.  x holds h on exit. */
+static void single_step(const qmat *sp, const qmat *z, qmat *zt, qmat *y, qmat *x, qmat *zn, double tau,
+                        double tau_s, double alpha, double eps, int64_t *ny, int64_t *nx, int64_t *nz) {
+    *ny = spamm(sp, z, y, tau_s, NULL, 0);
+    qmat_transpose(z, zt);
+    *nx = spamm(zt, y, x, tau, NULL, 0);
+    ns_map(x, alpha, eps);
     *nz = spamm(z, x, zn, tau, NULL, 0);
 }
 
@@ -449,6 +510,38 @@ int oracle_ns_step(const double *y_in, const double *z_in, double *y_out, double
     return ORC_OK;
 }
 
+/* One single-channel step from dense n x n s' and z (any z, not only
+ * iterates): y = s' (x)_{tau_s} z, zn = z (x)_tau h[z^T (x)_tau y] with the
+ * plain map. */
+int oracle_ns_single_step(const double *s_in, const double *z_in, double *y_out, double *z_out, int64_t n,
+                          int64_t b, double tau, double tau_s) {
+    if (n <= 0 || b <= 0 || !(tau >= 0.0)) return ORC_EINVAL;
+    if (tau_s < 0.0) tau_s = tau;
+    qmat sp, z, zt, y, x, zn;
+    int ok = qmat_alloc(&sp, n, b) == 0;
+    ok = ok && qmat_alloc(&z, n, b) == 0;
+    ok = ok && qmat_alloc(&zt, n, b) == 0;
+    ok = ok && qmat_alloc(&y, n, b) == 0;
+    ok = ok && qmat_alloc(&x, n, b) == 0;
+    ok = ok && qmat_alloc(&zn, n, b) == 0;
+    if (!ok) return ORC_ENOMEM;
+    load_padded(&sp, s_in, n);
+    load_padded(&z, z_in, n);
+    qmat_norms(&sp);
+    qmat_norms(&z);
+    int64_t ny, nx, nz;
+    single_step(&sp, &z, &zt, &y, &x, &zn, tau, tau_s, 1.0, 0.0, &ny, &nx, &nz);
+    store_logical(&y, y_out, n);
+    store_logical(&zn, z_out, n);
+    qmat_free(&sp);
+    qmat_free(&z);
+    qmat_free(&zt);
+    qmat_free(&y);
+    qmat_free(&x);
+    qmat_free(&zn);
+    return ORC_OK;
+}
+
 /*
  * oracle_ns_sqrt: y -> s^{1/2}, z -> s^{-1/2}.
  *
@@ -475,13 +568,18 @@ int oracle_ns_step(const double *y_in, const double *z_in, double *y_out, double
  *     y_{k+1} = h_k (x)_{tau_s} y_k ;  z_{k+1} = z_k (x)_tau h_k
  *   Returned: Y = sqrt(c) y_k, Z = z_k / sqrt(c) (logical n x n).
  *
+ * Single channel (single != 0; Sec. 3.2, eq. "single"): z_0 = I_n and for
+ *   k = 0, 1, ...: y_k = s' (x)_{tau_s} z_k, x_k = z_k^T (x)_tau y_k, the same
+ *   stop tests and map, z_{k+1} = z_k (x)_tau h_k; Y = sqrt(c) y_k.
+ *
  * Histories (optional, capacity maxit+1 entries): r_hist[k], t_hist[k],
- * nR_hist[3k..3k+2] = |R| of x_k, y_{k+1}, z_{k+1} (the last two 0 when no
- * update followed).  *iters = number of (y, z) updates performed.
+ * nR_hist[3k..3k+2] = |R| of x_k, y_{k+1}, z_{k+1} (dual; the last two 0
+ * when no update followed) or of x_k, y_k, z_{k+1} (single; the last 0 when
+ * no update followed).  *iters = number of updates performed.
  */
 int oracle_ns_sqrt(const double *s, double *Y, double *Z, int64_t n, int64_t b, double tau, double tau_s,
-                   double tol, int maxit, double mu_rel, int stagnation_stop, int damped, double *r_hist,
-                   double *t_hist, int64_t *nR_hist, int *iters, double *scale) {
+                   double tol, int maxit, double mu_rel, int stagnation_stop, int damped, int single,
+                   double *r_hist, double *t_hist, int64_t *nR_hist, int *iters, double *scale) {
     if (n <= 0 || b <= 0 || !(tau >= 0.0) || !(tol > 0.0) || maxit < 0 || !(mu_rel >= 0.0)) return ORC_EINVAL;
     if (tau_s < 0.0) tau_s = tau;
     int st = check_input(s, n);
@@ -514,41 +612,53 @@ int oracle_ns_sqrt(const double *s, double *Y, double *Z, int64_t n, int64_t b, 
 
     int status = ORC_NOT_CONVERGED;
     int k = 0;
-    double r0 = 0.0, r_best = 0.0;
-    int nondecrease = 0;
-    for (k = 0;; k++) {
-        int64_t nx = spamm(&y, &z, &x, tau, NULL, 0);
-        /* r_k and the trace over the logical block */
-        double r2 = 0.0, tr = 0.0;
-        for (int64_t i = 0; i < n; i++)
-            for (int64_t j = 0; j < n; j++) {
-                const double v = x.a[i * np + j];
-                const double e = (i == j ? 1.0 : 0.0) - v;
-                r2 += e * e;
-                if (i == j) tr += v;
-            }
-        const double r = sqrt(r2);
-        const double t = ((double)n - tr) / (double)n;
-        if (r_hist) r_hist[k] = r;
-        if (t_hist) t_hist[k] = t;
-        if (nR_hist) { nR_hist[3 * k] = nx; nR_hist[3 * k + 1] = 0; nR_hist[3 * k + 2] = 0; }
-        if (k == 0) r0 = r;
-        if (r < tol) { status = ORC_OK; break; }
-        if (!isfinite(r) || r > 10.0 * fmax(r0, sqrt((double)n))) { status = ORC_EDIVERGED; break; }
-        if (stagnation_stop && k > 0) {
-            const int settled = r_best < 0.5 || fabs(t) * (double)n < 0.5;
-            nondecrease = (settled && r >= 0.99 * r_best) ? nondecrease + 1 : 0;
-            if (nondecrease >= 2) { status = ORC_STAGNATED; break; }
+    stopper S = {0.0, 0.0, 0};
+    if (!single) {
+        for (k = 0;; k++) {
+            const int64_t nx = spamm(&y, &z, &x, tau, NULL, 0);
+            double r, t;
+            resid_trace(&x, &r, &t);
+            if (r_hist) r_hist[k] = r;
+            if (t_hist) t_hist[k] = t;
+            if (nR_hist) { nR_hist[3 * k] = nx; nR_hist[3 * k + 1] = 0; nR_hist[3 * k + 2] = 0; }
+            status = stop_test(&S, k, r, t, n, tol, maxit, stagnation_stop);
+            if (status != ORC_CONTINUE) break;
+            int64_t ny, nz;
+            double alpha, eps;
+            damping(damped, t, &alpha, &eps);
+            ns_update(&x, &y, &z, &yn, &zn, tau, tau_s, alpha, eps, &ny, &nz);
+            if (nR_hist) { nR_hist[3 * k + 1] = ny; nR_hist[3 * k + 2] = nz; }
+            qmat tmp = y; y = yn; yn = tmp;
+            tmp = z; z = zn; zn = tmp;
         }
-        if (k == 0 || r < r_best) r_best = r;
-        if (k == maxit) { status = ORC_NOT_CONVERGED; break; }
-        int64_t ny, nz;
-        double alpha, eps;
-        damping(damped, t, &alpha, &eps);
-        ns_update(&x, &y, &z, &yn, &zn, tau, tau_s, alpha, eps, &ny, &nz);
-        if (nR_hist) { nR_hist[3 * k + 1] = ny; nR_hist[3 * k + 2] = nz; }
-        qmat tmp = y; y = yn; yn = tmp;
-        tmp = z; z = zn; zn = tmp;
+    } else {
+        /* s' stays in sp; y_k is recomputed from it every iteration */
+        qmat sp = y, zt;
+        if (qmat_alloc(&zt, n, b)) {
+            qmat_free(&y); qmat_free(&z); qmat_free(&x); qmat_free(&yn); qmat_free(&zn);
+            return ORC_ENOMEM;
+        }
+        y = yn;  /* y_k */
+        for (k = 0;; k++) {
+            const int64_t ny = spamm(&sp, &z, &y, tau_s, NULL, 0);
+            qmat_transpose(&z, &zt);
+            const int64_t nx = spamm(&zt, &y, &x, tau, NULL, 0);
+            double r, t;
+            resid_trace(&x, &r, &t);
+            if (r_hist) r_hist[k] = r;
+            if (t_hist) t_hist[k] = t;
+            if (nR_hist) { nR_hist[3 * k] = nx; nR_hist[3 * k + 1] = ny; nR_hist[3 * k + 2] = 0; }
+            status = stop_test(&S, k, r, t, n, tol, maxit, stagnation_stop);
+            if (status != ORC_CONTINUE) break;
+            double alpha, eps;
+            damping(damped, t, &alpha, &eps);
+            ns_map(&x, alpha, eps);
+            const int64_t nz = spamm(&z, &x, &zn, tau, NULL, 0);
+            if (nR_hist) nR_hist[3 * k + 2] = nz;
+            qmat tmp = z; z = zn; zn = tmp;
+        }
+        yn = sp;  /* freed below with the others */
+        qmat_free(&zt);
     }
     const double sc = sqrt(c);
     for (int64_t i = 0; i < n; i++)

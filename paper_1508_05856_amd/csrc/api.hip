@@ -93,9 +93,11 @@ struct Plan {
     std::vector<unsigned long long> ids;
     int prec = 0, leaf = 0;
     bool damped = false;  // some solve of the set uses the damped map
+    bool single = false;  // single-channel solves (a plan holds one instance)
     char *mem = nullptr;
     size_t cap = 0;
-    ProdTable tx{}, tyz{};
+    ProdTable tx{}, tyz{};      // dual: x products; the y and z updates
+    ProdTable tt{}, ty{}, tz{}; // single: transposes z^T; y = s' z; z updates (x products in tx)
     SolveDesc *solves = nullptr;
     SolveState *gather = nullptr;
     SolveState *gather_host = nullptr;  // pinned
@@ -129,11 +131,13 @@ struct spamm_solve {
     Geom g;
     int prec;
     double tau, tau_s, tol, mu, c;
-    int maxit, stagnation, damped;
+    int maxit, stagnation, damped, single;
     char *mem;
     size_t bytes;
-    void *y[2], *z[2], *h;
-    double *qy[2], *qz[2], *qh, *ny[2], *nz[2], *nh;
+    // dual: y[parity], z[parity], h.  single: y[0] = s', y[1] = y_k, z[parity],
+    // zt = z_k^T, h.
+    void *y[2], *z[2], *h, *zt;
+    double *qy[2], *qz[2], *qh, *ny[2], *nz[2], *nh, *qzt, *nzt;
     int32_t *cnt[3], *kidx[3];
     double *part, *hist_r, *hist_t;
     int64_t *hist_nR;
@@ -279,6 +283,7 @@ ProdTable layout_table(Carve &c, const std::vector<ProdDesc> &prods, std::vector
 
 const double *root_of(const double *q, int P) { return q + level_off(P, 1); }
 
+// x = y (x)_tau z (dual), or x = z^T (x)_tau y_k (single)
 ProdDesc x_product(const spamm_solve *s) {
     ProdDesc d{};
     d.n = s->g.n;
@@ -286,13 +291,22 @@ ProdDesc x_product(const spamm_solve *s) {
     d.P = s->g.P;
     d.tau = s->tau;
     for (int q = 0; q < 2; ++q) {
-        d.A[q] = s->y[q];
-        d.B[q] = s->z[q];
+        if (s->single) {
+            d.A[q] = s->zt;
+            d.B[q] = s->y[1];
+            d.nrmA[q] = s->nzt;
+            d.nrmB[q] = s->ny[1];
+            d.rootA[q] = root_of(s->qzt, s->g.P);
+            d.rootB[q] = root_of(s->qy[1], s->g.P);
+        } else {
+            d.A[q] = s->y[q];
+            d.B[q] = s->z[q];
+            d.nrmA[q] = s->ny[q];
+            d.nrmB[q] = s->nz[q];
+            d.rootA[q] = root_of(s->qy[q], s->g.P);
+            d.rootB[q] = root_of(s->qz[q], s->g.P);
+        }
         d.C[q] = s->h;
-        d.nrmA[q] = s->ny[q];
-        d.nrmB[q] = s->nz[q];
-        d.rootA[q] = root_of(s->qy[q], s->g.P);
-        d.rootB[q] = root_of(s->qz[q], s->g.P);
         d.qC[q] = s->qh;
         d.nrmC[q] = s->nh;
     }
@@ -342,6 +356,53 @@ ProdDesc update_product(const spamm_solve *s, int which) {
     return d;
 }
 
+// Single instance: y_k = s' (x)_{tau_s} z_k.
+ProdDesc single_y_product(const spamm_solve *s) {
+    ProdDesc d{};
+    d.n = s->g.n;
+    d.nb = s->g.nb;
+    d.P = s->g.P;
+    d.tau = s->tau_s;
+    for (int q = 0; q < 2; ++q) {
+        d.A[q] = s->y[0];
+        d.B[q] = s->z[q];
+        d.C[q] = s->y[1];
+        d.nrmA[q] = s->ny[0];
+        d.nrmB[q] = s->nz[q];
+        d.rootA[q] = root_of(s->qy[0], s->g.P);
+        d.rootB[q] = root_of(s->qz[q], s->g.P);
+        d.qC[q] = s->qy[1];
+        d.nrmC[q] = s->ny[1];
+    }
+    d.cnt = s->cnt[1];
+    d.kidx = s->kidx[1];
+    d.state = s->state;
+    return d;
+}
+
+// Single instance: z_{k+1} = z_k (x)_tau h_k.
+ProdDesc single_z_product(const spamm_solve *s) {
+    ProdDesc d = update_product(s, 1);
+    return d;
+}
+
+// Single instance: zt = z_k^T (a transpose, not a product; the table entry
+// carries the source in A and the destination in C).
+ProdDesc transpose_desc(const spamm_solve *s) {
+    ProdDesc d{};
+    d.n = s->g.n;
+    d.nb = s->g.nb;
+    d.P = s->g.P;
+    for (int q = 0; q < 2; ++q) {
+        d.A[q] = s->z[q];
+        d.C[q] = s->zt;
+        d.qC[q] = s->qzt;
+        d.nrmC[q] = s->nzt;
+    }
+    d.state = s->state;
+    return d;
+}
+
 SolveDesc solve_desc(const spamm_solve *s) {
     SolveDesc d{};
     d.state = s->state;
@@ -350,6 +411,7 @@ SolveDesc solve_desc(const spamm_solve *s) {
     d.maxit = s->maxit;
     d.stagnation_stop = s->stagnation;
     d.damped = s->damped;
+    d.single = s->single;
     d.tol = s->tol;
     d.part = s->part;
     d.cnt_x = s->cnt[0];
@@ -393,17 +455,30 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
             *out = p;
             return SPAMM_OK;
         }
-    std::vector<ProdDesc> px, pyz;
+    const bool single = group[0]->single != 0;
+    std::vector<ProdDesc> px, pyz, pt, py, pz;
     std::vector<SolveDesc> sd;
     for (spamm_solve *s : group) {
         px.push_back(x_product(s));
-        pyz.push_back(update_product(s, 0));
-        pyz.push_back(update_product(s, 1));
+        if (single) {
+            pt.push_back(transpose_desc(s));
+            py.push_back(single_y_product(s));
+            pz.push_back(single_z_product(s));
+        } else {
+            pyz.push_back(update_product(s, 0));
+            pyz.push_back(update_product(s, 1));
+        }
         sd.push_back(solve_desc(s));
     }
     Carve sizing{nullptr, 0};
     layout_table(sizing, px, nullptr);
-    layout_table(sizing, pyz, nullptr);
+    if (single) {
+        layout_table(sizing, pt, nullptr);
+        layout_table(sizing, py, nullptr);
+        layout_table(sizing, pz, nullptr);
+    } else {
+        layout_table(sizing, pyz, nullptr);
+    }
     sizing.take<SolveDesc>(sd.size());
     sizing.take<SolveState>(sd.size());
     Plan *p = new Plan();
@@ -411,6 +486,7 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
     p->prec = group[0]->prec;
     p->leaf = group[0]->g.b;
     p->nsolve = (int)group.size();
+    p->single = single;
     p->damped = std::any_of(group.begin(), group.end(), [](const spamm_solve *s) { return s->damped != 0; });
     p->cap = sizing.off;
     hipError_t e = hipMalloc((void **)&p->mem, p->cap);
@@ -424,7 +500,13 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
     std::vector<char> image;
     Carve c{p->mem, 0};
     p->tx = layout_table(c, px, &image);
-    p->tyz = layout_table(c, pyz, &image);
+    if (single) {
+        p->tt = layout_table(c, pt, &image);
+        p->ty = layout_table(c, py, &image);
+        p->tz = layout_table(c, pz, &image);
+    } else {
+        p->tyz = layout_table(c, pyz, &image);
+    }
     const size_t o_sd = c.off;
     p->solves = c.take<SolveDesc>(sd.size());
     p->gather = c.take<SolveState>(sd.size());
@@ -451,6 +533,29 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
 // One Newton-Schulz iteration of every running solve of a plan.
 int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
     const int kp = kernel_prec(p->prec);
+    const int esz = (int)elt_size(p->prec);
+    if (p->single) {
+        // zt = z_k^T; y_k = s' (x)_{tau_s} z_k; x_k = zt (x)_tau y_k (+ stop test,
+        // map); z_{k+1} = z_k (x)_tau h_k
+        HIPCHK(launch_transpose_tab(kp, p->tt, p->leaf, st));
+        TIMED(K_PYR, launch_pyramid_tab(p->tt, st));
+        TIMED(K_CULL, launch_cull_tab(p->ty, st));
+        HIPCHK(launch_plan_tab(p->ty, p->leaf, esz, st));
+        TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->ty, st));
+        TIMED(K_PYR, launch_pyramid_tab(p->ty, st));
+        TIMED(K_CULL, launch_cull_tab(p->tx, st));
+        HIPCHK(launch_plan_tab(p->tx, p->leaf, esz, st));
+        TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
+        HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
+        if (p->damped) HIPCHK(launch_ns_map(kp, p->tx, p->leaf, st));
+        TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
+        TIMED(K_CULL, launch_cull_tab(p->tz, st));
+        HIPCHK(launch_plan_tab(p->tz, p->leaf, esz, st));
+        TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tz, st));
+        TIMED(K_PYR, launch_pyramid_tab(p->tz, st));
+        HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
+        return SPAMM_OK;
+    }
     TIMED(K_CULL, launch_cull_tab(p->tx, st));
     HIPCHK(launch_plan_tab(p->tx, p->leaf, (int)elt_size(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
@@ -490,16 +595,17 @@ int capture_iteration(spamm_ctx *ctx, Plan *p) {
     return SPAMM_OK;
 }
 
-size_t solve_bytes(const Geom &g, int prec, int maxit, spamm_solve *s) {
+size_t solve_bytes(const Geom &g, int prec, int maxit, int single, spamm_solve *s) {
     Carve c{s ? s->mem : nullptr, 0};
     const size_t tiles = (size_t)g.nb * g.nb * g.b * g.b * elt_size(prec);
     const size_t pyr = (size_t)pyr_len(g.P);
     const size_t nb2 = (size_t)g.nb * g.nb;
-    void *tl[5];
-    for (int i = 0; i < 5; ++i) tl[i] = c.take<char>(tiles);
-    double *q[5], *nr[5];
-    for (int i = 0; i < 5; ++i) q[i] = c.take<double>(pyr);
-    for (int i = 0; i < 5; ++i) nr[i] = c.take<double>(2 * nb2);  // leaf norms and their transpose
+    const int nmat = single ? 6 : 5;  // the single instance also holds z^T
+    void *tl[6] = {};
+    for (int i = 0; i < nmat; ++i) tl[i] = c.take<char>(tiles);
+    double *q[6] = {}, *nr[6] = {};
+    for (int i = 0; i < nmat; ++i) q[i] = c.take<double>(pyr);
+    for (int i = 0; i < nmat; ++i) nr[i] = c.take<double>(2 * nb2);  // leaf norms and their transpose
     int32_t *cnt[3], *kidx[3];
     for (int i = 0; i < 3; ++i) cnt[i] = c.take<int32_t>(nb2);
     for (int i = 0; i < 3; ++i) kidx[i] = c.take<int32_t>(nb2 * g.nb);
@@ -524,6 +630,9 @@ size_t solve_bytes(const Geom &g, int prec, int maxit, spamm_solve *s) {
         s->nz[0] = nr[2];
         s->nz[1] = nr[3];
         s->nh = nr[4];
+        s->zt = tl[5];
+        s->qzt = q[5];
+        s->nzt = nr[5];
         for (int i = 0; i < 3; ++i) {
             s->cnt[i] = cnt[i];
             s->kidx[i] = kidx[i];
@@ -558,6 +667,7 @@ spamm_ns_opts default_opts(const spamm_ns_opts *opts) {
     o.mu_rel = 0.0;
     o.stagnation_stop = 0;
     o.damped = 0;
+    o.single = 0;
     if (opts) {
         o = *opts;
         if (o.leaf == 0) o.leaf = 32;
@@ -752,10 +862,10 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     return status;
 }
 
-size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit) {
+size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit, int single) {
     if (n <= 0 || !valid_leaf(leaf) || !valid_prec(prec) || maxit < 0) return 0;
     const Geom g = make_geom(n, leaf);
-    return solve_bytes(g, prec, maxit, nullptr);
+    return solve_bytes(g, prec, maxit, single ? 1 : 0, nullptr);
 }
 
 int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, double tau, double tol, int maxit,
@@ -805,7 +915,8 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
     sv->stagnation = o.stagnation_stop ? 1 : 0;
     sv->damped = o.damped ? 1 : 0;
     sv->mem = nullptr;
-    sv->bytes = solve_bytes(g, o.prec, maxit, nullptr);
+    sv->single = o.single ? 1 : 0;
+    sv->bytes = solve_bytes(g, o.prec, maxit, sv->single, nullptr);
     hipError_t e = hipMalloc((void **)&sv->mem, sv->bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -813,7 +924,7 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
         return fail(SPAMM_ENOMEM, "solve allocation of %zu bytes failed: %s", (size_t)sv->bytes,
                     hipGetErrorString(e));
     }
-    solve_bytes(g, o.prec, maxit, sv);
+    solve_bytes(g, o.prec, maxit, sv->single, sv);
     const int kp = kernel_prec(o.prec);
     const size_t leafq = (size_t)g.P * g.P * sizeof(double);
     int rc = SPAMM_OK;
@@ -821,8 +932,8 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
         if (err != hipSuccess && rc == SPAMM_OK) rc = fail(SPAMM_EHIP, "%s failed: %s", what, hipGetErrorString(err));
     };
     // virtual blocks of every pyramid read as zero; records start empty
-    for (double *q : {sv->qy[0], sv->qy[1], sv->qz[0], sv->qz[1], sv->qh})
-        chk(hipMemsetAsync(q, 0, leafq, st), "memset");
+    for (double *q : {sv->qy[0], sv->qy[1], sv->qz[0], sv->qz[1], sv->qh, sv->qzt})
+        if (q) chk(hipMemsetAsync(q, 0, leafq, st), "memset");
     chk(hipMemsetAsync(sv->hist_nR, 0, 3 * (size_t)(maxit + 1) * sizeof(int64_t), st), "memset");
     chk(launch_ingest(kp, s, ld, mu, c, g, sv->y[0], sv->qy[0], st), "ingest");
     chk(launch_identity(kp, g, sv->z[0], sv->qz[0], st), "identity");
@@ -856,7 +967,7 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
             if (solves[j] == s) return fail(SPAMM_EINVAL, "solve %d appears twice", i);
         if (s->host_state.status != ST_RUNNING) continue;
         auto it = std::find_if(groups.begin(), groups.end(), [&](const std::vector<spamm_solve *> &gr) {
-            return gr[0]->prec == s->prec && gr[0]->g.b == s->g.b;
+            return gr[0]->prec == s->prec && gr[0]->g.b == s->g.b && gr[0]->single == s->single;
         });
         if (it == groups.end())
             groups.push_back({s});
@@ -923,7 +1034,7 @@ int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *s, double *Y, double *Z, int
     const int kp = kernel_prec(s->prec);
     const double sc = std::sqrt(s->c);
     const int k = h.k;
-    if (Y) HIPCHK(launch_egress(kp, s->g, s->y[h.parity], Y, ld, sc, 0, st));
+    if (Y) HIPCHK(launch_egress(kp, s->g, s->single ? s->y[1] : s->y[h.parity], Y, ld, sc, 0, st));
     if (Z) HIPCHK(launch_egress(kp, s->g, s->z[h.parity], Z, ld, sc, 1, st));
     ctx->hist_r.assign(k + 1, 0.0);
     ctx->hist_t.assign(k + 1, 0.0);

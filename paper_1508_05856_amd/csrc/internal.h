@@ -53,6 +53,7 @@ struct SolveDesc {
     int nb;
     int maxit, stagnation_stop;
     int damped;          // the map's alpha(t), eps(t) are set from t_k (else alpha = 1, eps = 0)
+    int single;          // single-channel instance: cnt_y counts y_k of this iteration
     double tol;
     const double *part;  // nb*nb*2: per-tile (sum (I-x)^2, trace x) of the x product
     const int32_t *cnt_x, *cnt_y, *cnt_z;
@@ -148,6 +149,9 @@ hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t s
 hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st);  // pyramid of each product's C
 // Per solve: r_k, t_k, |R| records and the stop decision.
 hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, hipStream_t st);
+// Transpose of each running product's A (current parity) into its C, with
+// C's leaf squared norms: tile (i,j) of C is tile (j,i) of A transposed.
+hipError_t launch_transpose_tab(int prec, const ProdTable &t, int leaf, hipStream_t st);
 // Damped map of every damped running solve's x product, in place:
 // h = (sqrt(alpha)/2) (3 I - alpha (eps I + (1 - 2 eps) x)), and h's leaf norms.
 hipError_t launch_ns_map(int prec, const ProdTable &t, int leaf, hipStream_t st);

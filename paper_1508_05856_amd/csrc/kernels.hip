@@ -1,6 +1,7 @@
 // HIP kernels for gfx950 (CDNA4): input checks and ingest, the Frobenius-norm
-// pyramid, the two-sided cull, the leaf products on MFMA with the fused
-// Newton-Schulz epilogue, reductions and egress.
+// pyramid, the two-sided cull and the job lists of the leaf products (whose
+// kernels are in leaf_gemm.hip), Newton-Schulz control and map, reductions and
+// egress.
 //
 // Layout in HBM: every operand is tile-major, b x b tiles each contiguous and
 // row-major inside, tile (i,k) at offset (i*nb + k)*b*b.  The pyramid holds
@@ -9,6 +10,7 @@
 
 #include <cstdint>
 
+#include "device.h"
 #include "internal.h"
 
 namespace spk {
@@ -48,51 +50,6 @@ void tile_order(int nb, int32_t *order) {
         }
         if (i < nb && j < nb) order[m++] = i * nb + j;
     }
-}
-
-__device__ inline int64_t dev_level_off(int P, int S) {
-    int64_t o = 0;
-    for (int64_t T = P; T > S; T >>= 1) o += T * T;
-    return o;
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ inline double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Block-wide sum in a fixed order: lanes by xor-butterfly, then waves 0..W-1.
-template <int NT>
-__device__ inline double block_sum(double v, double *sh) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < NT / 64; ++i) t += sh[i];
-    return t;  // valid in thread 0
-}
-
-template <int NT>
-__device__ inline double block_max(double v, double *sh) {
-    v = wave_max(v);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < NT / 64; ++i) t = fmax(t, sh[i]);
-    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -333,27 +290,6 @@ hipError_t launch_pyramid(const Geom &g, double *q0, double *nrm0, double *q1, d
     }
     return hipGetLastError();
 }
-
-// ---------------------------------------------------------------------------
-// Product tables.  Every batched launch covers all products of a table; a
-// block finds its product by binary search in a prefix array and returns at
-// once when the product's solve is not running.
-// ---------------------------------------------------------------------------
-__device__ inline int find_slot(const int32_t *pre, int n, int x) {
-    // largest p in [0, n) with pre[p] <= x  (pre[0] = 0 <= x < pre[n])
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= x)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ inline bool prod_running(const ProdDesc &d) { return d.state == nullptr || d.state->status == ST_RUNNING; }
-__device__ inline int prod_parity(const ProdDesc &d) { return d.state ? d.state->parity : 0; }
 
 // Pyramid of each running product's C: pass 1 on the leaf level, pass 2 (one
 // block per product with P > 32) from level P/32 to the root.
@@ -605,491 +541,6 @@ hipError_t launch_plan_tab(const ProdTable &t, int leaf, int esz, hipStream_t st
 }
 
 // ---------------------------------------------------------------------------
-// Leaf products on MFMA.  One workgroup per output tile, taken from the
-// longest-first work list; 64x64 tiles use four waves, each owning a 32x32
-// quadrant (2x2 blocks of 16x16), 32x32 and 16x16 tiles one wave.  The
-// retained k of the tile are consumed in increasing order, in pipeline
-// stages (half a tile of k for 64x64 tiles): each stage of A_ik and B_kj goes
-// global -> registers -> one of two LDS buffers, two stages ahead of the
-// MFMAs that use it.
-// Epilogue: the C tile and its squared norm (of the stored values, FP64);
-// for a Newton-Schulz x product the tile written is h = 1.5 I_n - 0.5 x, with
-// the FP64 partial sums of (I_n - x)^2 and of the trace over the logical block.
-// ---------------------------------------------------------------------------
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef double d2 __attribute__((ext_vector_type(2)));
-
-// Pointers read from job records are generic; marking them global lets the
-// compiler use global (not flat) loads and stores, whose completion is
-// tracked apart from LDS traffic.
-template <typename T>
-using gptr = T __attribute__((address_space(1))) *;
-template <typename T>
-__device__ inline gptr<T> to_global(T *p) {
-    return (gptr<T>)p;
-}
-
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-    typedef v4d acc_t;
-    typedef d2 vec_t;  // 16-byte chunk
-    static constexpr int VEC = 2;
-    __device__ static inline acc_t mma(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    // accumulator element r of lane l holds row l/16 + 4r, column l%16
-    __device__ static inline int row_of(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-template <>
-struct Mfma<float> {
-    typedef v4f acc_t;
-    typedef v4f vec_t;
-    static constexpr int VEC = 4;
-    __device__ static inline acc_t mma(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    // accumulator element r of lane l holds row 4(l/16) + r, column l%16
-    __device__ static inline int row_of(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-
-template <typename T, int B>
-struct TileCfg {
-    static constexpr int WAVES = (B == 64) ? 4 : 1;
-    static constexpr int NT = 64 * WAVES;
-    static constexpr int Q = (B >= 32) ? 32 : 16;  // rows/cols of C per wave
-    static constexpr int NBLK = Q / 16;            // 16x16 MFMA blocks per wave side
-    static constexpr int VEC = Mfma<T>::VEC;       // elements per 16-byte chunk
-    static constexpr int KS = (B == 64) ? 32 : B;  // k extent of one pipeline stage
-    static constexpr int SPT = B / KS;             // stages per retained triple
-    // LDS row strides (elements).  A stage (B x KS) is read by fragments
-    // A[row + l%16][k + l/16]: a stride of KS + 16 bytes puts the 16 rows and
-    // the k offsets of a 32-lane (FP64) or 64-lane (FP32) access in distinct
-    // banks.  B stage (KS x B) is read as B[k + l/16][col + l%16]: a stride of
-    // B + 16 elements moves consecutive k rows by half (FP64) or a quarter
-    // (FP32) of the 64 banks.
-    static constexpr int LDA = KS + VEC;
-    static constexpr int LDB = (B == 16) ? 16 : B + 16;
-    static constexpr int A_CH = B * KS / VEC / NT;  // 16-byte chunks per thread per stage
-    static constexpr int B_CH = KS * B / VEC / NT;
-};
-
-template <typename T, int B>
-__global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(const Job *__restrict__ jobs,
-                                                                    const int32_t *__restrict__ work_count) {
-    using C = TileCfg<T, B>;
-    using M = Mfma<T>;
-    typedef typename M::acc_t acc_t;
-    typedef typename M::vec_t vec_t;
-    // two pipeline buffers for each operand
-    __shared__ __attribute__((aligned(16))) T As[2][B * C::LDA];
-    __shared__ __attribute__((aligned(16))) T Bs[2][C::KS * C::LDB];
-    __shared__ double red[3 * C::WAVES];
-
-    // both loads are issued before the test (the job array always has a
-    // record for every block of the grid)
-    const int nwork = *work_count;
-    const Job J = jobs[blockIdx.x];
-    if ((int)blockIdx.x >= nwork) return;
-    const bool nsx = J.part != nullptr;
-    const int nb = J.nb;
-    const int i = J.i, j = J.j;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wr = (C::WAVES == 4) ? (w >> 1) : 0, wc = (C::WAVES == 4) ? (w & 1) : 0;
-    const int cnt = J.cnt;
-    const gptr<const int32_t> list = to_global(J.list);
-    const gptr<const T> Arow = to_global((const T *)J.a_row);
-    const gptr<const T> Bcol = to_global((const T *)J.b_col);
-    constexpr int64_t TS = (int64_t)B * B;
-    const int S = cnt * C::SPT;  // pipeline stages
-
-    acc_t acc[C::NBLK][C::NBLK];
-#pragma unroll
-    for (int bi = 0; bi < C::NBLK; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < C::NBLK; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0;
-
-    // stage s covers k-columns [ks*KS, ks*KS+KS) of triple (i, j, list[s/SPT])
-    auto gload = [&](int s, vec_t *ra, vec_t *rb) {
-        const int e = s / C::SPT;
-        const int k = e == 0 ? J.k0 : (e == 1 ? J.k1 : list[e]);
-        const int ks = s % C::SPT;
-        const gptr<const T> a = Arow + (int64_t)k * TS + ks * C::KS;
-        const gptr<const vec_t> b = (gptr<const vec_t>)(Bcol + (int64_t)k * nb * TS + (int64_t)ks * C::KS * B);
-#pragma unroll
-        for (int c = 0; c < C::A_CH; ++c) {
-            const int el = (tid + c * C::NT) * C::VEC;
-            ra[c] = *(gptr<const vec_t>)(a + (el / C::KS) * B + el % C::KS);
-        }
-#pragma unroll
-        for (int c = 0; c < C::B_CH; ++c) rb[c] = b[tid + c * C::NT];
-    };
-    auto sstore = [&](int buf, const vec_t *ra, const vec_t *rb) {
-#pragma unroll
-        for (int c = 0; c < C::A_CH; ++c) {
-            const int el = (tid + c * C::NT) * C::VEC;
-            *(vec_t *)&As[buf][(el / C::KS) * C::LDA + el % C::KS] = ra[c];
-        }
-#pragma unroll
-        for (int c = 0; c < C::B_CH; ++c) {
-            const int el = (tid + c * C::NT) * C::VEC;
-            *(vec_t *)&Bs[buf][(el / B) * C::LDB + el % B] = rb[c];
-        }
-    };
-    auto compute = [&](int buf) {
-#pragma unroll
-        for (int kk = 0; kk < C::KS; kk += 4) {
-            T av[C::NBLK], bv[C::NBLK];
-#pragma unroll
-            for (int bi = 0; bi < C::NBLK; ++bi)
-                av[bi] = As[buf][(wr * C::Q + bi * 16 + (lane & 15)) * C::LDA + kk + (lane >> 4)];
-#pragma unroll
-            for (int bj = 0; bj < C::NBLK; ++bj)
-                bv[bj] = Bs[buf][(kk + (lane >> 4)) * C::LDB + wc * C::Q + bj * 16 + (lane & 15)];
-#pragma unroll
-            for (int bi = 0; bi < C::NBLK; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < C::NBLK; ++bj) acc[bi][bj] = M::mma(av[bi], bv[bj], acc[bi][bj]);
-        }
-    };
-
-    // Software pipeline: LDS buffers alternate; register sets R0/R1 hold the
-    // stages two and one ahead of the one being multiplied, so every global
-    // load has two stages of MFMA work to arrive.  One barrier per stage.
-    vec_t ra0[C::A_CH], rb0[C::B_CH], ra1[C::A_CH], rb1[C::B_CH];
-    if (S > 0) {
-        gload(0, ra0, rb0);
-        if (S > 1) gload(1, ra1, rb1);
-        sstore(0, ra0, rb0);
-        if (S > 2) gload(2, ra0, rb0);
-    }
-    __syncthreads();
-    for (int s = 0; s < S; s += 2) {
-        // even stage s: LDS buffer 0; stage s+1 waits in R1, stage s+2 in R0
-        if (s + 1 < S) sstore(1, ra1, rb1);
-        if (s + 3 < S) gload(s + 3, ra1, rb1);
-        compute(0);
-        __syncthreads();
-        if (s + 1 >= S) break;
-        // odd stage s+1: LDS buffer 1; stage s+2 waits in R0, stage s+3 in R1
-        if (s + 2 < S) sstore(0, ra0, rb0);
-        if (s + 4 < S) gload(s + 4, ra0, rb0);
-        compute(1);
-        __syncthreads();
-    }
-
-    // epilogue
-    const gptr<T> Ct = to_global((T *)J.c);
-    double qs = 0.0, r2 = 0.0, tr = 0.0;
-#pragma unroll
-    for (int bi = 0; bi < C::NBLK; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < C::NBLK; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = wr * C::Q + bi * 16 + M::row_of(lane, r);
-                const int col = wc * C::Q + bj * 16 + (lane & 15);
-                const double x = (double)acc[bi][bj][r];
-                T out;
-                if (nsx) {
-                    const int64_t gi = (int64_t)i * B + row, gj = (int64_t)j * B + col;
-                    const bool diag = (gi == gj) && (gi < J.n);
-                    const bool logical = (gi < J.n) && (gj < J.n);
-                    const double h = (diag ? 1.5 : 0.0) - 0.5 * x;
-                    const double ex = (diag ? 1.0 : 0.0) - x;
-                    if (logical) r2 += ex * ex;
-                    if (diag) tr += x;
-                    out = J.fused_map ? (T)h : (T)x;
-                } else {
-                    out = (T)x;
-                }
-                Ct[row * B + col] = out;
-                const double dv = (double)out;
-                qs += dv * dv;
-            }
-    qs = wave_sum(qs);
-    if (nsx) {
-        r2 = wave_sum(r2);
-        tr = wave_sum(tr);
-    }
-    if (lane == 0) {
-        red[w] = qs;
-        red[C::WAVES + w] = r2;
-        red[2 * C::WAVES + w] = tr;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double a = 0.0, b = 0.0, c = 0.0;
-        for (int x = 0; x < C::WAVES; ++x) {
-            a += red[x];
-            b += red[C::WAVES + x];
-            c += red[2 * C::WAVES + x];
-        }
-        *to_global(J.qc) = a;
-        if (nsx) {
-            to_global(J.part)[0] = b;
-            to_global(J.part)[1] = c;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// BF16x3 leaf products.  Operands stay FP32 in HBM (norms and the cull use
-// those stored values); while a stage is staged into LDS every element is
-// split into bf16 planes, x = hi + lo with hi = bf16(x) and lo = bf16(x - hi)
-// (round to nearest even, x - hi exact), and each 16x16x32 block product is
-// hi*hi + hi*lo + lo*hi on the bf16 matrix cores, accumulated in FP32.  The
-// dropped lo*lo term and the split residual are O(2^-16) of |a||b|.
-// A is staged row-major (k contiguous per row); B is staged transposed (k
-// contiguous per column), the k pairs being packed by the conversion itself,
-// so both MFMA operands are single 16-byte LDS reads.
-// ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float f2 __attribute__((ext_vector_type(2)));
-
-template <int B>
-struct Bf3Cfg {
-    static constexpr int WAVES = (B == 64) ? 4 : 1;
-    static constexpr int NT = 64 * WAVES;
-    static constexpr int Q = 32;                // rows/cols of C per wave
-    static constexpr int NBLK = 2;              // 16x16 blocks per wave side
-    static constexpr int KS = 32;               // k of one stage = k of one MFMA
-    static constexpr int SPT = B / KS;          // stages per retained triple
-    static constexpr int LDK = KS + 8;          // bf16 per LDS row: 16-byte pad keeps 16-lane reads conflict-free
-    static constexpr int A_CH = B * KS / 4 / NT;         // float4 chunks of A per thread per stage
-    static constexpr int B_UN = (KS / 2) * (B / 4) / NT;  // (k pair, 4 columns) units of B per thread
-};
-
-// hi/lo split of two FP32 values into packed bf16 pairs
-__device__ inline void split2(float x0, float x1, unsigned &hi, unsigned &lo) {
-    const f2 v = {x0, x1};
-    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
-    const f2 hv = {__builtin_bit_cast(float, hi << 16), __builtin_bit_cast(float, hi & 0xffff0000u)};
-    const f2 d = v - hv;
-    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(d, bf16x2));
-}
-
-template <int B>
-__global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Job *__restrict__ jobs,
-                                                                        const int32_t *__restrict__ work_count) {
-    using C = Bf3Cfg<B>;
-    // [buffer][plane hi/lo][rows x LDK]
-    __shared__ __attribute__((aligned(16))) __bf16 As[2][2][B * C::LDK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bt[2][2][B * C::LDK];
-    __shared__ double red[3 * C::WAVES];
-
-    const int nwork = *work_count;
-    const Job J = jobs[blockIdx.x];
-    if ((int)blockIdx.x >= nwork) return;
-    const bool nsx = J.part != nullptr;
-    const int nb = J.nb;
-    const int i = J.i, j = J.j;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wr = (C::WAVES == 4) ? (w >> 1) : 0, wc = (C::WAVES == 4) ? (w & 1) : 0;
-    const int cnt = J.cnt;
-    const gptr<const int32_t> list = to_global(J.list);
-    const gptr<const float> Arow = to_global((const float *)J.a_row);
-    const gptr<const float> Bcol = to_global((const float *)J.b_col);
-    constexpr int64_t TS = (int64_t)B * B;
-    const int S = cnt * C::SPT;
-
-    v4f acc[C::NBLK][C::NBLK];
-#pragma unroll
-    for (int bi = 0; bi < C::NBLK; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < C::NBLK; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0.0f;
-
-    // stage s: k-columns [ks*KS, ks*KS+KS) of triple (i, j, list[s/SPT]).
-    // A chunk c: 4 consecutive k of one row.  B unit u: rows 2kp and 2kp+1
-    // (a k pair) of 4 consecutive columns 4cg..4cg+3.
-    auto gload = [&](int s, v4f *ra, v4f *rb) {
-        const int e = s / C::SPT;
-        const int k = e == 0 ? J.k0 : (e == 1 ? J.k1 : list[e]);
-        const int ks = s % C::SPT;
-        const gptr<const float> a = Arow + (int64_t)k * TS + ks * C::KS;
-        const gptr<const float> b = Bcol + (int64_t)k * nb * TS + (int64_t)ks * C::KS * B;
-#pragma unroll
-        for (int c = 0; c < C::A_CH; ++c) {
-            const int el = (tid + c * C::NT) * 4;
-            ra[c] = *(gptr<const v4f>)(a + (el / C::KS) * B + el % C::KS);
-        }
-#pragma unroll
-        for (int c = 0; c < C::B_UN; ++c) {
-            const int u = tid + c * C::NT;
-            const int kp = u % (C::KS / 2), cg = u / (C::KS / 2);
-            rb[2 * c] = *(gptr<const v4f>)(b + (2 * kp) * B + 4 * cg);
-            rb[2 * c + 1] = *(gptr<const v4f>)(b + (2 * kp + 1) * B + 4 * cg);
-        }
-    };
-    auto sstore = [&](int buf, const v4f *ra, const v4f *rb) {
-#pragma unroll
-        for (int c = 0; c < C::A_CH; ++c) {
-            const int el = (tid + c * C::NT) * 4;
-            const int row = el / C::KS, k = el % C::KS;
-            unsigned h0, l0, h1, l1;
-            split2(ra[c][0], ra[c][1], h0, l0);
-            split2(ra[c][2], ra[c][3], h1, l1);
-            typedef unsigned u2 __attribute__((ext_vector_type(2)));
-            *(u2 *)&As[buf][0][row * C::LDK + k] = u2{h0, h1};
-            *(u2 *)&As[buf][1][row * C::LDK + k] = u2{l0, l1};
-        }
-#pragma unroll
-        for (int c = 0; c < C::B_UN; ++c) {
-            const int u = tid + c * C::NT;
-            const int kp = u % (C::KS / 2), cg = u / (C::KS / 2);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                unsigned h, l;
-                split2(rb[2 * c][q], rb[2 * c + 1][q], h, l);  // (k, k+1) of column 4cg+q
-                const int col = 4 * cg + q;
-                *(unsigned *)&Bt[buf][0][col * C::LDK + 2 * kp] = h;
-                *(unsigned *)&Bt[buf][1][col * C::LDK + 2 * kp] = l;
-            }
-        }
-    };
-    auto compute = [&](int buf) {
-        // operand layout of the 16x16x32 bf16 MFMA: lane l supplies row (A) or
-        // column (B) l%16 at k = 8(l/16) .. 8(l/16)+7
-        bf16x8 ah[C::NBLK], al[C::NBLK], bh[C::NBLK], bl[C::NBLK];
-        const int ko = 8 * (lane >> 4);
-#pragma unroll
-        for (int bi = 0; bi < C::NBLK; ++bi) {
-            const int row = wr * C::Q + bi * 16 + (lane & 15);
-            ah[bi] = *(const bf16x8 *)&As[buf][0][row * C::LDK + ko];
-            al[bi] = *(const bf16x8 *)&As[buf][1][row * C::LDK + ko];
-        }
-#pragma unroll
-        for (int bj = 0; bj < C::NBLK; ++bj) {
-            const int col = wc * C::Q + bj * 16 + (lane & 15);
-            bh[bj] = *(const bf16x8 *)&Bt[buf][0][col * C::LDK + ko];
-            bl[bj] = *(const bf16x8 *)&Bt[buf][1][col * C::LDK + ko];
-        }
-#pragma unroll
-        for (int bi = 0; bi < C::NBLK; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < C::NBLK; ++bj) {
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-            }
-    };
-
-    // same two-stage-ahead software pipeline as the FP32/FP64 kernel
-    v4f ra0[C::A_CH], rb0[2 * C::B_UN], ra1[C::A_CH], rb1[2 * C::B_UN];
-    if (S > 0) {
-        gload(0, ra0, rb0);
-        if (S > 1) gload(1, ra1, rb1);
-        sstore(0, ra0, rb0);
-        if (S > 2) gload(2, ra0, rb0);
-    }
-    __syncthreads();
-    for (int s = 0; s < S; s += 2) {
-        if (s + 1 < S) sstore(1, ra1, rb1);
-        if (s + 3 < S) gload(s + 3, ra1, rb1);
-        compute(0);
-        __syncthreads();
-        if (s + 1 >= S) break;
-        if (s + 2 < S) sstore(0, ra0, rb0);
-        if (s + 4 < S) gload(s + 4, ra0, rb0);
-        compute(1);
-        __syncthreads();
-    }
-
-    // epilogue (FP32 tile out; FP64 norms and Newton-Schulz partials)
-    const gptr<float> Ct = to_global((float *)J.c);
-    double qs = 0.0, r2 = 0.0, tr = 0.0;
-#pragma unroll
-    for (int bi = 0; bi < C::NBLK; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < C::NBLK; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = wr * C::Q + bi * 16 + 4 * (lane >> 4) + r;
-                const int col = wc * C::Q + bj * 16 + (lane & 15);
-                const double x = (double)acc[bi][bj][r];
-                float out;
-                if (nsx) {
-                    const int64_t gi = (int64_t)i * B + row, gj = (int64_t)j * B + col;
-                    const bool diag = (gi == gj) && (gi < J.n);
-                    const bool logical = (gi < J.n) && (gj < J.n);
-                    const double h = (diag ? 1.5 : 0.0) - 0.5 * x;
-                    const double ex = (diag ? 1.0 : 0.0) - x;
-                    if (logical) r2 += ex * ex;
-                    if (diag) tr += x;
-                    out = J.fused_map ? (float)h : (float)x;
-                } else {
-                    out = (float)x;
-                }
-                Ct[row * B + col] = out;
-                const double dv = (double)out;
-                qs += dv * dv;
-            }
-    qs = wave_sum(qs);
-    if (nsx) {
-        r2 = wave_sum(r2);
-        tr = wave_sum(tr);
-    }
-    if (lane == 0) {
-        red[w] = qs;
-        red[C::WAVES + w] = r2;
-        red[2 * C::WAVES + w] = tr;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double a = 0.0, b = 0.0, c = 0.0;
-        for (int x = 0; x < C::WAVES; ++x) {
-            a += red[x];
-            b += red[C::WAVES + x];
-            c += red[2 * C::WAVES + x];
-        }
-        *to_global(J.qc) = a;
-        if (nsx) {
-            to_global(J.part)[0] = b;
-            to_global(J.part)[1] = c;
-        }
-    }
-}
-
-template <typename T, int B>
-static void gemm_launch(const ProdTable &t, hipStream_t st) {
-    hipLaunchKernelGGL((k_leaf_gemm<T, B>), dim3(t.total_tiles), dim3(TileCfg<T, B>::NT), 0, st, t.jobs,
-                       t.work_count);
-}
-
-template <typename T>
-static void gemm_dispatch_b(int leaf, const ProdTable &t, hipStream_t st) {
-    if (leaf == 64)
-        gemm_launch<T, 64>(t, st);
-    else if (leaf == 32)
-        gemm_launch<T, 32>(t, st);
-    else
-        gemm_launch<T, 16>(t, st);
-}
-
-hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t st) {
-    if (prec == P_F64) {
-        gemm_dispatch_b<double>(leaf, t, st);
-    } else if (prec == P_BF16X3) {
-        if (leaf == 64)
-            hipLaunchKernelGGL(k_leaf_gemm_bf3<64>, dim3(t.total_tiles), dim3(256), 0, st, t.jobs, t.work_count);
-        else if (leaf == 32)
-            hipLaunchKernelGGL(k_leaf_gemm_bf3<32>, dim3(t.total_tiles), dim3(64), 0, st, t.jobs, t.work_count);
-        else
-            return hipErrorInvalidValue;
-    } else {
-        gemm_dispatch_b<float>(leaf, t, st);
-    }
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Newton-Schulz control, one workgroup per solve: r_k = sqrt(sum of per-tile
 // (I-x)^2), t_k = (n - trace)/n and the retained-triple counts, summed in a
 // fixed order, then the stop tests in the order: r_k < tol (OK); r_k not
@@ -1104,15 +555,16 @@ __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict_
     if (st->status != ST_RUNNING) return;
     const int k = st->k;
     const int64_t ntiles = (int64_t)sd.nb * sd.nb;
+    // the y product of the single instance precedes x_k; the dual instance's
+    // y and z products, and the single instance's z product, belong to k-1
+    const bool have_y = sd.single || k > 0, have_z = k > 0;
     double r2 = 0.0, tr = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
     for (int64_t e = threadIdx.x; e < ntiles; e += 1024) {
         r2 += sd.part[2 * e];
         tr += sd.part[2 * e + 1];
         cx += (double)sd.cnt_x[e];
-        if (k > 0) {
-            cy += (double)sd.cnt_y[e];
-            cz += (double)sd.cnt_z[e];
-        }
+        if (have_y) cy += (double)sd.cnt_y[e];
+        if (have_z) cz += (double)sd.cnt_z[e];
     }
     r2 = block_sum<1024>(r2, sh);
     tr = block_sum<1024>(tr, sh);
@@ -1125,7 +577,10 @@ __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict_
     sd.hist_r[k] = r;
     sd.hist_t[k] = tk;
     sd.hist_nR[3 * k] = (int64_t)cx;
-    if (k > 0) {
+    if (sd.single) {
+        sd.hist_nR[3 * k + 1] = (int64_t)cy;
+        if (k > 0) sd.hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
+    } else if (k > 0) {
         sd.hist_nR[3 * (k - 1) + 1] = (int64_t)cy;
         sd.hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
     }
@@ -1165,6 +620,41 @@ __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict_
     st->alpha = alpha;
     st->eps = eps;
     st->status = status;
+}
+
+// Tile transpose, one workgroup per output tile, through LDS (b <= 64).
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_tab(const ProdDesc *__restrict__ prods,
+                                                       const int32_t *__restrict__ pre, int nprod, int b) {
+    __shared__ T buf[64][65];
+    __shared__ double sh[4];
+    const int p = find_slot(pre, nprod, blockIdx.x);
+    const ProdDesc &d = prods[p];
+    if (!prod_running(d)) return;
+    const int par = prod_parity(d);
+    const int nb = d.nb, t = blockIdx.x - pre[p], i = t / nb, j = t % nb;
+    const T *src = (const T *)d.A[par] + ((int64_t)j * nb + i) * b * b;
+    T *dst = (T *)d.C[par] + (int64_t)t * b * b;
+    for (int e = threadIdx.x; e < b * b; e += 256) buf[e / b][e % b] = src[e];
+    __syncthreads();
+    double q = 0.0;
+    for (int e = threadIdx.x; e < b * b; e += 256) {
+        const T v = buf[e % b][e / b];
+        dst[e] = v;
+        q += (double)v * (double)v;
+    }
+    q = block_sum<256>(q, sh);
+    if (threadIdx.x == 0) d.qC[par][(int64_t)i * d.P + j] = q;
+}
+
+hipError_t launch_transpose_tab(int prec, const ProdTable &t, int leaf, hipStream_t st) {
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_transpose_tab<double>, dim3(t.total_tiles), dim3(256), 0, st, t.prods, t.tile_pre,
+                           t.nprod, leaf);
+    else
+        hipLaunchKernelGGL(k_transpose_tab<float>, dim3(t.total_tiles), dim3(256), 0, st, t.prods, t.tile_pre,
+                           t.nprod, leaf);
+    return hipGetLastError();
 }
 
 // Damped map, one workgroup per tile of the x products of a table, in place.

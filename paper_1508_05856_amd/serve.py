@@ -34,6 +34,7 @@ class Request:
     mu_rel: float = 0.0
     stagnation_stop: bool = True
     damped: bool = False
+    single: bool = False
     t_submit: float = 0.0
     future: Future = field(default_factory=Future)
     footprint: int = 0
@@ -79,7 +80,7 @@ class Server:
     # -- client side ----------------------------------------------------------
     def submit(self, s: torch.Tensor, tau: float, tol: float, **kw) -> Future:
         req = Request(s=s, tau=tau, tol=tol, **kw)
-        req.footprint = self.ctx.footprint(s.shape[0], req.leaf, req.prec, req.maxit)
+        req.footprint = self.ctx.footprint(s.shape[0], req.leaf, req.prec, req.maxit, req.single)
         if req.footprint == 0 or req.footprint > self.hbm_budget:
             req.future.set_exception(ValueError(f"request needs {req.footprint} bytes; budget {self.hbm_budget}"))
             return req.future
@@ -120,7 +121,8 @@ class Server:
             try:
                 sv = self.ctx.solve_begin(req.s, req.tau, req.tol, req.maxit, leaf=req.leaf, prec=req.prec,
                                           tau_s=req.tau_s, mu_rel=req.mu_rel,
-                                          stagnation_stop=req.stagnation_stop, damped=req.damped)
+                                          stagnation_stop=req.stagnation_stop, damped=req.damped,
+                                          single=req.single)
             except Exception as e:  # invalid input or no memory: fail this request only
                 req.s = None
                 req.future.set_exception(e)

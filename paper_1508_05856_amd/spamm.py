@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
 
 class NsOpts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("prec", ctypes.c_int), ("tau_s", ctypes.c_double),
-                ("mu_rel", ctypes.c_double), ("stagnation_stop", ctypes.c_int), ("damped", ctypes.c_int)]
+                ("mu_rel", ctypes.c_double), ("stagnation_stop", ctypes.c_int), ("damped", ctypes.c_int),
+                ("single", ctypes.c_int)]
 
 
 class NsResult(ctypes.Structure):
@@ -80,7 +81,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.ns_sqrt.argtypes = [vp, vp, vp, vp, i64, i64, dbl, dbl, ctypes.c_int, ctypes.POINTER(NsOpts),
                                 ctypes.POINTER(NsResult), vp]
         lib.spamm_ns_history.argtypes = [vp, vp, vp, vp, ctypes.c_int]
-        lib.spamm_solve_footprint.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.spamm_solve_footprint.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.spamm_solve_footprint.restype = ctypes.c_size_t
         lib.spamm_solve_begin.argtypes = [vp, vp, i64, i64, dbl, dbl, ctypes.c_int, ctypes.POINTER(NsOpts),
                                           ctypes.POINTER(ctypes.c_void_p), vp]
@@ -187,7 +188,8 @@ class Context:
 
     def ns_sqrt(self, s: torch.Tensor, tau: float, tol: float, maxit: int, leaf: int = 32, prec="f64",
                 tau_s: float = -1.0, mu_rel: float = 0.0, stagnation_stop: bool = False, damped: bool = False,
-                Y: torch.Tensor | None = None, Z: torch.Tensor | None = None, raise_on_error: bool = True):
+                single: bool = False, Y: torch.Tensor | None = None, Z: torch.Tensor | None = None,
+                raise_on_error: bool = True):
         """Y ~ s^{1/2}, Z ~ s^{-1/2}.  Returns (Y, Z, info dict)."""
         ps, ld = _mat(s, "s")
         n = s.shape[0]
@@ -198,7 +200,7 @@ class Context:
         if ldy != ld or ldz != ld:
             raise ValueError("Y and Z must share s's leading dimension")
         opts = NsOpts(leaf, _PREC[prec] if isinstance(prec, str) else int(prec), float(tau_s), float(mu_rel),
-                      int(bool(stagnation_stop)), int(bool(damped)))
+                      int(bool(stagnation_stop)), int(bool(damped)), int(bool(single)))
         res = NsResult()
         status = self.lib.ns_sqrt(self.handle, ps, py, pz, n, ld, float(tau), float(tol), int(maxit),
                                   ctypes.byref(opts), ctypes.byref(res), _stream_ptr(s.device))
@@ -211,16 +213,16 @@ class Context:
         return Y, Z, info
 
     # -- step API (batched and served solves) --------------------------------
-    def footprint(self, n: int, leaf: int, prec="f64", maxit: int = 40) -> int:
+    def footprint(self, n: int, leaf: int, prec="f64", maxit: int = 40, single: bool = False) -> int:
         return int(self.lib.spamm_solve_footprint(n, leaf, _PREC[prec] if isinstance(prec, str) else int(prec),
-                                                  maxit))
+                                                  maxit, int(bool(single))))
 
     def solve_begin(self, s: torch.Tensor, tau: float, tol: float, maxit: int, leaf: int = 32, prec="f64",
                     tau_s: float = -1.0, mu_rel: float = 0.0, stagnation_stop: bool = False,
-                    damped: bool = False) -> "Solve":
+                    damped: bool = False, single: bool = False) -> "Solve":
         ps, ld = _mat(s, "s")
         opts = NsOpts(leaf, _PREC[prec] if isinstance(prec, str) else int(prec), float(tau_s), float(mu_rel),
-                      int(bool(stagnation_stop)), int(bool(damped)))
+                      int(bool(stagnation_stop)), int(bool(damped)), int(bool(single)))
         h = ctypes.c_void_p()
         _check(self.lib.spamm_solve_begin(self.handle, ps, s.shape[0], ld, float(tau), float(tol), int(maxit),
                                           ctypes.byref(opts), ctypes.byref(h), _stream_ptr(s.device)))

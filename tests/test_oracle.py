@@ -519,3 +519,52 @@ def test_damped_map_converges_to_the_root_in_fewer_updates():
     assert damped["iterations"] <= plain["iterations"] - 4
     Yr, Zr = eig_sqrt(s)
     assert rel(damped["Y"], Yr) < 1e-9 and rel(damped["Z"], Zr) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Single-channel instance (Sec. 3.2, eq. "single"): z_{k+1} = z_k h[x_k],
+# x_k = z_k^T s z_k, with y_k = s' (x)_{tau_s} z_k the implicit y channel
+# ---------------------------------------------------------------------------
+
+def test_single_step_at_tau_zero_is_the_definition():
+    """From a non-symmetric z (so a misplaced transpose or a swapped operand
+    order shows), one step at tau = 0 is y = s' z, z' = z (3I - z^T s' z)/2."""
+    n, leaf = 100, 16
+    sp = inputs.kms(n, 0.6) / 2.4
+    z = np.eye(n) + 0.05 * np.random.default_rng(5).standard_normal((n, n))
+    y, zn = oracle.ns_single_step(sp, z, leaf, 0.0)
+    np.testing.assert_allclose(y, sp @ z, rtol=0, atol=1e-14)
+    x = z.T @ (sp @ z)
+    ref = z @ (1.5 * np.eye(n) - 0.5 * x)
+    np.testing.assert_allclose(zn, ref, rtol=0, atol=1e-13)
+    assert np.abs(zn - z @ (1.5 * np.eye(n) - 0.5 * (z @ sp @ z))).max() > 1e-4   # the transpose matters
+
+
+@pytest.mark.parametrize("kind", ["kms", "gauss"])
+def test_single_channel_at_tau_zero_converges_like_dual(kind):
+    """Exact products: z_k stays a polynomial in s', so the single and dual
+    instances follow the same spectral recurrence (same update count) and
+    reach the same roots (eigendecomposition)."""
+    s = inputs.kms(256, 0.7) if kind == "kms" else inputs.gauss_gramian(6, 1.0)
+    dual = oracle.ns_sqrt(s, 32, 0.0, 1e-10, 40)
+    single = oracle.ns_sqrt(s, 32, 0.0, 1e-10, 40, single=True)
+    assert single["status"] == oracle.OK and single["iterations"] == dual["iterations"]
+    np.testing.assert_allclose(single["r"], dual["r"], rtol=1e-6, atol=1e-12)
+    Yr, Zr = eig_sqrt(s)
+    assert rel(single["Y"], Yr) < 1e-10 and rel(single["Z"], Zr) < 1e-10
+    assert single["nR"][0, 1] > 0 and single["nR"][-1, 2] == 0
+
+
+def test_single_channel_damped_and_tau():
+    """The damped map and a positive tau carry over: damped single converges
+    at tau = 0 in fewer updates; at tau > 0 it stops on its floor close to
+    the roots."""
+    s = inputs.gauss_gramian(8, 0.8)
+    plain = oracle.ns_sqrt(s, 32, 0.0, 1e-10, 60, single=True)
+    damped = oracle.ns_sqrt(s, 32, 0.0, 1e-10, 60, single=True, damped=True)
+    assert plain["status"] == oracle.OK and damped["status"] == oracle.OK
+    assert damped["iterations"] <= plain["iterations"] - 4
+    res = oracle.ns_sqrt(inputs.kms(512, 0.7), 32, 1e-8, 1e-10, 40, single=True, stagnation_stop=True)
+    assert res["status"] == oracle.STAGNATED
+    Yr, Zr = eig_sqrt(inputs.kms(512, 0.7))
+    assert rel(res["Y"], Yr) < 1e-5 and rel(res["Z"], Zr) < 1e-5
