@@ -27,6 +27,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}
+LEAF_SRC = os.path.join(ROOT, "paper_1508_05856_amd", "csrc", "leaf_gemm.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "leaf_gemm_f64_gauss_n4096_b64_tau1e-8_traffic.md")
+
+
+def committed_traffic(workload: str, prec: str):
+    """HBM bytes per leaf-product launch (FETCH_SIZE + WRITE_SIZE, each
+    scaled by the same counter on a plain copy of known size) from the
+    committed counter profile of this workload, or None when there is none
+    or the leaf-product source has changed since it was taken."""
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_PROFILE).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    sha = hashlib.sha256(open(LEAF_SRC, "rb").read()).hexdigest()
+    if rec.get("leaf_gemm_sha256") != sha or rec.get("workload") != workload or rec.get("prec") != prec:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def parse():
@@ -441,7 +462,8 @@ def main():
         },
         "roofline": {
             "bound": "mfma", "kernel": "k_leaf_gemm_bf3" if args.prec == "bf16x3" else "k_leaf_gemm", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "useful_tflops": useful,
+            "frac": achieved / peak, "traffic": committed_traffic(cfg["name"], args.prec),
+            "traffic_unit": "bytes per launch", "useful_tflops": useful,
             "launches": len(gemm_ms), "avg_launch_ms": float(np.mean(gemm_ms)),
             "gemm_ms_per_step": sum(gemm_ms) / args.steps,
             "cull_ms_per_step": sum(cull_ms) / args.steps, "pyramid_ms_per_step": sum(pyr_ms) / args.steps,
