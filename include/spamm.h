@@ -124,14 +124,15 @@ typedef struct {
                             eigenvalue of an exact iterate is within 1/2 of 1, where an
                             update shrinks r more than 2x: no 1% gain means the
                             tau/rounding floor)                                         */
-    int damped;          /* 1 = the damped map of Sec. 4.3 "Mapping": h = (sqrt(a)/2)
+    int damped;          /* 1 = the damped map of Sec. 4.2 "Mapping": h = (sqrt(a)/2)
                             (3 I - a xs), xs = e I + (1 - 2e) x, with the scaling
                             a(t) = 1 + 1.85/(1 + exp(-50 (t - 0.35))) and stabilisation
                             e(t) = 0.1/(1 + exp(-75 (t - 0.30))) of the trace error
                             t_k = (n - tr x_k)/n; both switched off (a = 1, e = 0) once
                             t_k < 0.1, so the fixed point stays x = I.  0 = the plain
                             map h = 1.5 I - 0.5 x                                       */
-    int single;          /* 1 = the single-channel instance (Sec. 3.2, eq. "single"):
+    int single;          /* 1 = the single-channel instance (Sec. 3.2, eq. "single";
+                            the implicit y channel as described in Sec. 5.3):
                             z_0 = I_n; y_k = s' (x)_{tau_s} z_k (the y channel implicit in
                             the product with s, taken rightmost at the tighter tau_s),
                             x_k = z_k^T (x)_tau y_k, z_{k+1} = z_k (x)_tau h_k; Y = sqrt(c)
@@ -205,6 +206,17 @@ int spamm_solve_poll(spamm_solve *solve, int *done, spamm_ns_result *res);
  * the solve's history for spamm_ns_history, frees the solve and returns its
  * status (NOT_CONVERGED if it was still running).  Synchronises. */
 int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *solve, double *Y, double *Z, int64_t ld, void *stream);
+
+/* Retained (i, j, k) leaf triples of the most recent product of one channel
+ * of a solve (the "vol" of Secs. 5.4 and 6.2 and the ijk volumes shown for lensing,
+ * Sec. 7.2): which = 0 the x product, 1 the y product, 2 the z product.
+ * After a step the x product is that of the last iteration performed; the
+ * y and z products are those of the last update (in the single instance the
+ * y product is y_k of the last iteration).  triples: DEVICE int32[cap][3],
+ * sorted by (i, j, k); *count (HOST, optional) receives |R|; ECAPACITY (and
+ * the count) when |R| > cap.  Synchronises the stream. */
+int spamm_solve_triples(spamm_ctx *ctx, spamm_solve *solve, int which, int32_t *triples, int64_t cap,
+                        int64_t *count, void *stream);
 
 /* Per-iteration record of the most recent finished solve on this context, HOST
  * outputs of capacity cap entries: r[k], t[k] and nR[3k..3k+2] = |R| of x_k,

@@ -147,7 +147,7 @@ def spamm_tiles(a, b, leaf: int, tau: float, tiles):
 def ns_sqrt(s, leaf: int, tau: float, tol: float, maxit: int, tau_s: float = -1.0, mu_rel: float = 0.0,
             stagnation_stop: bool = False, damped: bool = False, single: bool = False) -> dict:
     """Coupled Newton-Schulz, dual channel or (single=True) the single
-    channel instance, optionally with the damped map of Sec. 4.3.  Returns a
+    channel instance, optionally with the damped map of Sec. 4.2.  Returns a
     dict with Y, Z, status, iterations, scale and the r, t and |R| histories."""
     s = _f64(s)
     n = s.shape[0]

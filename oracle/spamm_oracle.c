@@ -374,7 +374,7 @@ static int check_input(const double *s, int64_t n) {
     return ORC_OK;
 }
 
-/* Damping of the map (Sec. 4.3 "Mapping"): the scaling
+/* Damping of the map (Sec. 4.2 "Mapping"): the scaling
  *   alpha(t) = 1 + 1.85 / (1 + exp(-50 (t - 0.35)))
  * and the stabilisation eps(t) = 0.1 / (1 + exp(-75 (t - 0.30))), both driven
  * by the relative trace error t_k.  The paper turns both off towards

@@ -1015,6 +1015,30 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
     return running;
 }
 
+int spamm_solve_triples(spamm_ctx *ctx, spamm_solve *s, int which, int32_t *triples, int64_t cap, int64_t *count,
+                        void *stream) {
+    TRY(enter(ctx));
+    if (!s || s->ctx != ctx) return fail(SPAMM_EINVAL, "NULL solve or solve of another context");
+    if (which < 0 || which > 2) return fail(SPAMM_EINVAL, "which must be 0 (x), 1 (y) or 2 (z)");
+    if (cap < 0 || (cap > 0 && !triples)) return fail(SPAMM_EINVAL, "bad triple buffer");
+    hipStream_t st = (hipStream_t)stream;
+    const Geom &g = s->g;
+    const size_t nb2 = (size_t)g.nb * g.nb;
+    TRY(ensure(ctx, S_OFFS, nb2 * sizeof(int64_t)));
+    int64_t *offs = slot_ptr<int64_t>(ctx, S_OFFS);
+    int64_t *total = reinterpret_cast<int64_t *>(slot_ptr<double>(ctx, S_SCAL) + 8);
+    HIPCHK(launch_count_triples(g, s->cnt[which], offs, total, st));
+    HIPCHK(hipMemcpyAsync(ctx->pinned, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t m;
+    std::memcpy(&m, ctx->pinned, sizeof(int64_t));
+    if (count) *count = m;
+    if (m > cap) return fail(SPAMM_ECAPACITY, "|R| = %lld exceeds triple capacity %lld", (long long)m, (long long)cap);
+    if (m > 0) HIPCHK(launch_write_triples(g, s->cnt[which], s->kidx[which], offs, triples, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SPAMM_OK;
+}
+
 int spamm_solve_poll(spamm_solve *s, int *done, spamm_ns_result *res) {
     if (!s) return fail(SPAMM_EINVAL, "NULL solve");
     const int st = s->host_state.status;

@@ -609,7 +609,7 @@ __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict_
             if (k == sd.maxit) status = 1;  // SPAMM_NOT_CONVERGED
         }
     }
-    // damped map (Sec. 4.3): scaling alpha(t) and stabilisation eps(t) of the
+    // damped map (Sec. 4.2): scaling alpha(t) and stabilisation eps(t) of the
     // trace error, both switched off once t_k < 0.1 (the sigmoids never reach
     // 1 and 0 exactly; eps(0) alone would hold r above sqrt(n) 1.7e-11)
     double alpha = 1.0, eps = 0.0;

@@ -28,7 +28,7 @@ STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", STAGNATED: "STAGNATED"
 EXPORTS = ("spamm_create", "spamm_destroy", "spamm_last_error", "spamm_pyramid_len", "spamm_norms",
            "spamm_multiply", "ns_sqrt", "spamm_ns_history", "spamm_solve_footprint", "spamm_solve_begin",
            "spamm_solve_step", "spamm_solve_poll", "spamm_solve_finish", "spamm_set_graphs", "spamm_profile_enable",
-           "spamm_profile_read", "spamm_profile_reset")
+           "spamm_profile_read", "spamm_profile_reset", "spamm_solve_triples")
 KIND_GEMM, KIND_CULL, KIND_PYRAMID = 0, 1, 2
 
 
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.spamm_solve_step.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, vp]
         lib.spamm_solve_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(NsResult)]
         lib.spamm_solve_finish.argtypes = [vp, vp, vp, vp, i64, vp]
+        lib.spamm_solve_triples.argtypes = [vp, vp, ctypes.c_int, vp, i64, ctypes.POINTER(ctypes.c_int64), vp]
         lib.spamm_profile_enable.argtypes = [vp, ctypes.c_int]
         lib.spamm_set_graphs.argtypes = [vp, ctypes.c_int]
         lib.spamm_set_graphs.restype = ctypes.c_int
@@ -267,6 +268,19 @@ class Solve:
 
     def __init__(self, ctx: Context, handle, n: int, device):
         self.ctx, self.handle, self.n, self.device = ctx, handle, n, device
+
+    def triples(self, which: int) -> torch.Tensor:
+        """Retained (i, j, k) triples of the latest product of one channel
+        (0 = x, 1 = y, 2 = z), sorted, as a device int32 tensor (|R|, 3)."""
+        cnt = ctypes.c_int64(0)
+        # a zero-capacity call reports the count (ECAPACITY when non-empty)
+        self.ctx.lib.spamm_solve_triples(self.ctx.handle, self.handle, int(which), None, 0, ctypes.byref(cnt),
+                                         _stream_ptr(self.device))
+        m = int(cnt.value)
+        out = torch.empty((max(m, 1), 3), dtype=torch.int32, device=self.device)
+        _check(self.ctx.lib.spamm_solve_triples(self.ctx.handle, self.handle, int(which), out.data_ptr(), m,
+                                                ctypes.byref(cnt), _stream_ptr(self.device)))
+        return out[:m]
 
     def poll(self) -> dict:
         done = ctypes.c_int(0)

@@ -453,7 +453,7 @@ def test_ns_status_codes():
 
 
 # ---------------------------------------------------------------------------
-# Damped map (Sec. 4.3): alpha(t), eps(t) driven by the trace error, switched
+# Damped map (Sec. 4.2): alpha(t), eps(t) driven by the trace error, switched
 # off once t_k < 0.1
 # ---------------------------------------------------------------------------
 
