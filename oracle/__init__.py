@@ -59,6 +59,10 @@ def _load():
                                            ctypes.c_int, ctypes.c_int, dp, dp, lp, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_double)]
             lib.oracle_ns_single_step.argtypes = [dp, dp, dp, dp, i64, i64, ctypes.c_double, ctypes.c_double]
+            lib.oracle_product_rep.argtypes = [dp, dp, i64, i64, dp, ctypes.c_int, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_int, ip, ip]
+            lib.oracle_product_rep.restype = ctypes.c_int
             for f in (lib.oracle_norms, lib.oracle_spamm, lib.oracle_spamm_tiles, lib.oracle_ns_sqrt,
                       lib.oracle_ns_step, lib.oracle_ns_single_step):
                 f.restype = ctypes.c_int
@@ -194,3 +198,21 @@ def ns_single_step(s, z, leaf: int, tau: float, tau_s: float = -1.0):
     if st:
         raise OracleError(f"oracle_ns_single_step status {st}")
     return y, zn
+
+
+def product_rep(s, leaf: int, mu_rel, tau_slice: float, tau_r: float, tol: float, maxit: int,
+                tau_s_slice: float = -1.0, stagnation_stop: bool = True, damped: bool = False) -> dict:
+    """Inverse factor W of s + mu_rel[-1] c0 I as a product of regularised
+    slices (Secs. 6.1, 6.3).  Returns dict(status, W, statuses, iterations)."""
+    s = _f64(s)
+    n = s.shape[0]
+    mu = np.ascontiguousarray(np.asarray(mu_rel, dtype=np.float64))
+    W = np.zeros_like(s)
+    sts = np.zeros(len(mu), dtype=np.int32)
+    its = np.zeros(len(mu), dtype=np.int32)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    st = _load().oracle_product_rep(_dptr(s), _dptr(W), n, leaf, _dptr(mu), len(mu), float(tau_slice),
+                                    float(tau_s_slice), float(tau_r), float(tol), int(maxit),
+                                    int(bool(stagnation_stop)), int(bool(damped)), sts.ctypes.data_as(ip),
+                                    its.ctypes.data_as(ip))
+    return dict(status=st, W=W, statuses=sts.tolist(), iterations=its.tolist())

@@ -675,3 +675,75 @@ int oracle_ns_sqrt(const double *s, double *Y, double *Z, int64_t n, int64_t b, 
     qmat_free(&zn);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Product representation of the regularised inverse factor (Sec. 6.1), built */
+/* by iterative regularisation (Sec. 6.3).                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Slice 0: W = (s + mu_0 c0 I)^{-1/2} by Newton-Schulz at the slice
+ * threshold (the coarse first slice).  Then for each finer shift mu_j
+ * (j = 1 .. nslices-1): the residual congruence
+ *   M_j = W^T (x)_{tau_r} ((s + mu_j c0 I) (x)_{tau_r} W),
+ * taken through its symmetric part (M_j + M_j^T)/2 (symmetric in exact
+ * arithmetic), is itself a well-conditioned matrix; Z_j = M_j^{-1/2} by
+ * Newton-Schulz at the slice threshold, and W <- W (x)_{tau_r} Z_j, so that
+ * W^T (s + mu_j c0 I) W -> I.  The new slice multiplies on the right, the
+ * order under which that congruence holds; the paper writes the slices in the
+ * reverse order, equal in exact arithmetic since every factor is a function
+ * of s.  c0 is the Gershgorin bound of s; the residual products use the
+ * (tighter) threshold tau_r.  statuses[j], iters[j] receive each slice's
+ * Newton-Schulz status and update count.  Returns the first negative slice
+ * status, else OK.
+ */
+int oracle_product_rep(const double *s, double *W, int64_t n, int64_t b, const double *mu_rel, int nslices,
+                       double tau_slice, double tau_s_slice, double tau_r, double tol, int maxit,
+                       int stagnation_stop, int damped, int *statuses, int *iters) {
+    if (n <= 0 || b <= 0 || nslices < 1 || !mu_rel || !(tau_r >= 0.0)) return ORC_EINVAL;
+    int st = check_input(s, n);
+    if (st) return st;
+    const size_t nn = (size_t)(n * n);
+    double *Y = (double *)malloc(nn * sizeof(double));
+    double *S = (double *)malloc(nn * sizeof(double));
+    double *T = (double *)malloc(nn * sizeof(double));
+    double *Wt = (double *)malloc(nn * sizeof(double));
+    double *M = (double *)malloc(nn * sizeof(double));
+    double *Z = (double *)malloc(nn * sizeof(double));
+    if (!Y || !S || !T || !Wt || !M || !Z) {
+        free(Y); free(S); free(T); free(Wt); free(M); free(Z);
+        return ORC_ENOMEM;
+    }
+    const double c0 = gershgorin(s, n);
+    int it = 0;
+    double sc;
+    st = oracle_ns_sqrt(s, Y, W, n, b, tau_slice, tau_s_slice, tol, maxit, mu_rel[0], stagnation_stop, damped, 0,
+                        NULL, NULL, NULL, &it, &sc);
+    if (statuses) statuses[0] = st;
+    if (iters) iters[0] = it;
+    for (int j = 1; j < nslices && st >= 0; j++) {
+        memcpy(S, s, nn * sizeof(double));
+        const double mu = mu_rel[j] * c0;
+        for (int64_t i = 0; i < n; i++) S[i * n + i] += mu;
+        int64_t cnt;
+        oracle_spamm(S, W, T, n, b, tau_r, NULL, 0, &cnt);
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t k = 0; k < n; k++) Wt[k * n + i] = W[i * n + k];
+        oracle_spamm(Wt, T, M, n, b, tau_r, NULL, 0, &cnt);
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t k = i; k < n; k++) {
+                const double v = 0.5 * (M[i * n + k] + M[k * n + i]);
+                M[i * n + k] = v;
+                M[k * n + i] = v;
+            }
+        st = oracle_ns_sqrt(M, Y, Z, n, b, tau_slice, tau_s_slice, tol, maxit, 0.0, stagnation_stop, damped, 0,
+                            NULL, NULL, NULL, &it, &sc);
+        if (statuses) statuses[j] = st;
+        if (iters) iters[j] = it;
+        if (st < 0) break;
+        oracle_spamm(W, Z, T, n, b, tau_r, NULL, 0, &cnt);
+        memcpy(W, T, nn * sizeof(double));
+    }
+    free(Y); free(S); free(T); free(Wt); free(M); free(Z);
+    return st < 0 ? st : ORC_OK;
+}

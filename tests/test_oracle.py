@@ -568,3 +568,51 @@ def test_single_channel_damped_and_tau():
     assert res["status"] == oracle.STAGNATED
     Yr, Zr = eig_sqrt(inputs.kms(512, 0.7))
     assert rel(res["Y"], Yr) < 1e-5 and rel(res["Z"], Zr) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Product representation by iterative regularisation (Secs. 6.1, 6.3)
+# ---------------------------------------------------------------------------
+
+def shifted(s, mu_rel):
+    return s + mu_rel * np.abs(s).sum(axis=1).max() * np.eye(s.shape[0])
+
+
+def test_product_rep_at_tau_zero_is_the_inverse_root_of_the_last_shift():
+    """Exact slices and congruences: W^T s_mu W = I exactly at every slice, and
+    since every factor is a function of s, W = (s + mu_m c0 I)^{-1/2}."""
+    s = inputs.gauss_gramian(6, 0.8)
+    mus = [1e-2, 1e-3, 1e-4]
+    res = oracle.product_rep(s, 32, mus, 0.0, 0.0, 1e-10, 40)
+    assert res["status"] == oracle.OK and res["statuses"] == [oracle.OK] * 3
+    _, Zr = eig_sqrt(shifted(s, mus[-1]))
+    assert rel(res["W"], Zr) < 1e-10
+
+
+def test_product_rep_one_slice_is_the_shifted_solve():
+    s = inputs.kms(300, 0.8)
+    res = oracle.product_rep(s, 32, [1e-3], 1e-6, 1e-9, 1e-10, 40, tau_s_slice=1e-8)
+    ns = oracle.ns_sqrt(s, 32, 1e-6, 1e-10, 40, tau_s=1e-8, mu_rel=1e-3, stagnation_stop=True)
+    assert res["iterations"] == [ns["iterations"]]
+    np.testing.assert_array_equal(res["W"], ns["Z"])
+
+
+def test_product_rep_preconditions_by_orders_of_magnitude():
+    """Coarse slices (tau 1e-4) with residuals at 1e-8: the congruence
+    W^T s_mu W of the last shift is near the identity although s_mu itself has
+    kappa ~ 7.7e3 (kappa(s) ~ 8e5)."""
+    s = inputs.gauss_gramian(8, 0.8)
+    mus = [1e-1, 1e-2, 1e-3, 1e-4]
+    res = oracle.product_rep(s, 32, mus, 1e-4, 1e-8, 1e-10, 40, tau_s_slice=1e-6, damped=True)
+    assert res["status"] == oracle.OK
+    Sm = shifted(s, mus[-1])
+    E = res["W"].T @ Sm @ res["W"]
+    ev = np.linalg.eigvalsh(0.5 * (E + E.T))
+    ws = np.linalg.eigvalsh(Sm)
+    assert ws[-1] / ws[0] > 5e3 and ev[-1] / ev[0] < 2.0
+
+
+def test_product_rep_reports_a_diverging_slice():
+    s = inputs.gauss_gramian(8, 0.8)
+    res = oracle.product_rep(s, 32, [1e-1, 1e-2, 1e-3], 1e-2, 1e-6, 1e-10, 40, tau_s_slice=1e-4, damped=True)
+    assert res["status"] == oracle.EDIVERGED and res["statuses"][0] >= 0 and oracle.EDIVERGED in res["statuses"]
