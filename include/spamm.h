@@ -218,6 +218,46 @@ int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *solve, double *Y, double *Z,
 int spamm_solve_triples(spamm_ctx *ctx, spamm_solve *solve, int which, int32_t *triples, int64_t cap,
                         int64_t *count, void *stream);
 
+/*
+ * Product representation of the regularised inverse factor (Sec. 6.1) by
+ * iterative regularisation (Sec. 6.3).  Slice 0: W = (s + mu_0 c0 I)^{-1/2}
+ * by ns_sqrt at the slice threshold (c0 the Gershgorin bound of s).  Then for
+ * each finer shift mu_j: the residual congruence M_j = W^T (x)_{tau_r}
+ * ((s + mu_j c0 I) (x)_{tau_r} W), through its symmetric part (symmetric in
+ * exact arithmetic); Z_j = M_j^{-1/2} by ns_sqrt at the slice threshold; and
+ * W <- W (x)_{tau_r} Z_j, so that W^T (s + mu_j c0 I) W -> I.  The new slice
+ * multiplies on the right, the order under which that congruence holds (the
+ * paper prints the reverse order, equal in exact arithmetic).
+ */
+#define SPAMM_MAX_SLICES 16
+typedef struct {
+    int leaf;               /* N_b of every product and solve; 0 = 32                      */
+    int prec;               /* spamm_prec of every product and solve                       */
+    int nslices;            /* 1 .. SPAMM_MAX_SLICES                                       */
+    const double *mu_rel;   /* HOST, nslices shifts relative to c0, each >= 0 (decreasing)  */
+    double tau_slice;       /* tau of each slice's Newton-Schulz solve                      */
+    double tau_s_slice;     /* its tau_s; < 0 = tau_slice                                    */
+    double tau_r;           /* tau of the residual congruences and of the slice products    */
+    double tol;             /* each slice's stop tolerance                                   */
+    int maxit;              /* each slice's update limit                                     */
+    int stagnation_stop;    /* as spamm_ns_opts                                              */
+    int damped;             /* as spamm_ns_opts                                              */
+} spamm_prodrep_opts;
+
+typedef struct {
+    int nslices_done;                    /* slices computed (stops at a failing slice)   */
+    int status[SPAMM_MAX_SLICES];        /* each slice's ns_sqrt status                  */
+    int iterations[SPAMM_MAX_SLICES];    /* each slice's update count                    */
+} spamm_prodrep_result;
+
+/* s: DEVICE, symmetric (as ns_sqrt); W: DEVICE output, row-major with
+ * leading dimension ld >= n.  Working memory (six n x ld FP64 matrices) is
+ * allocated for the call and freed before it returns.  Returns the first
+ * negative slice status (EDIVERGED: W holds the last good factor), EINVAL,
+ * ENOMEM, EHIP, else OK.  res: optional HOST output.  Synchronises. */
+int spamm_product_rep(spamm_ctx *ctx, const double *s, double *W, int64_t n, int64_t ld,
+                      const spamm_prodrep_opts *opts, spamm_prodrep_result *res, void *stream);
+
 /* Per-iteration record of the most recent finished solve on this context, HOST
  * outputs of capacity cap entries: r[k], t[k] and nR[3k..3k+2] = |R| of x_k,
  * y_{k+1}, z_{k+1} (the last two are 0 where no update followed).  Returns the

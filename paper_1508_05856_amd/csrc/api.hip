@@ -1015,6 +1015,92 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
     return running;
 }
 
+namespace {
+
+// Slices of the product representation into W, with six n x ld working
+// matrices S, T, Wt, M, Y, Z; returns the first failing status.
+int product_rep_body(spamm_ctx *ctx, const double *s, double *W, int64_t n, int64_t ld, const spamm_prodrep_opts &o,
+                     int leaf, double *const *buf, spamm_prodrep_result *res, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    double *S = buf[0], *T = buf[1], *Wt = buf[2], *M = buf[3], *Y = buf[4], *Z = buf[5];
+    spamm_ns_opts no{};
+    no.leaf = leaf;
+    no.prec = o.prec;
+    no.tau_s = o.tau_s_slice;
+    no.stagnation_stop = o.stagnation_stop;
+    no.damped = o.damped;
+    // c0 = Gershgorin bound of s (the column sums ns_sqrt uses)
+    TRY(ensure(ctx, S_CHECK, (size_t)n * sizeof(double)));
+    TRY(ensure(ctx, S_SCAL, 64 * sizeof(double)));
+    double *out = slot_ptr<double>(ctx, S_SCAL);
+    HIPCHK(launch_colsum_max(s, n, ld, 0.0, slot_ptr<double>(ctx, S_CHECK), out, st));
+    HIPCHK(hipMemcpyAsync(ctx->pinned, out, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double c0 = ctx->pinned[0];
+    spamm_ns_result nr{};
+    for (int j = 0; j < o.nslices; ++j) {
+        int sj;
+        if (j == 0) {
+            no.mu_rel = o.mu_rel[0];
+            sj = ns_sqrt(ctx, s, Y, W, n, ld, o.tau_slice, o.tol, o.maxit, &no, &nr, stream);
+        } else {
+            HIPCHK(launch_shift_copy(s, S, n, ld, o.mu_rel[j] * c0, st));
+            TRY(spamm_multiply(ctx, S, W, T, n, ld, o.tau_r, leaf, o.prec, nullptr, 0, nullptr, stream));
+            HIPCHK(launch_transpose_dense(W, Wt, n, ld, st));
+            TRY(spamm_multiply(ctx, Wt, T, M, n, ld, o.tau_r, leaf, o.prec, nullptr, 0, nullptr, stream));
+            HIPCHK(launch_sym_part(M, S, n, ld, st));
+            no.mu_rel = 0.0;
+            sj = ns_sqrt(ctx, S, Y, Z, n, ld, o.tau_slice, o.tol, o.maxit, &no, &nr, stream);
+        }
+        if (res) {
+            res->status[j] = sj;
+            res->iterations[j] = nr.iterations;
+            res->nslices_done = j + 1;
+        }
+        if (sj < 0) return sj;
+        if (j > 0) {
+            TRY(spamm_multiply(ctx, W, Z, T, n, ld, o.tau_r, leaf, o.prec, nullptr, 0, nullptr, stream));
+            HIPCHK(hipMemcpyAsync(W, T, (size_t)n * ld * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return SPAMM_OK;
+}
+
+}  // namespace
+
+int spamm_product_rep(spamm_ctx *ctx, const double *s, double *W, int64_t n, int64_t ld,
+                      const spamm_prodrep_opts *opts, spamm_prodrep_result *res, void *stream) {
+    if (!opts) return fail(SPAMM_EINVAL, "NULL options");
+    const spamm_prodrep_opts o = *opts;
+    const int leaf = o.leaf == 0 ? 32 : o.leaf;
+    TRY(validate_common(ctx, s, n, ld, leaf));
+    TRY(enter(ctx));
+    if (!W) return fail(SPAMM_EINVAL, "NULL output pointer");
+    if (o.nslices < 1 || o.nslices > SPAMM_MAX_SLICES)
+        return fail(SPAMM_EINVAL, "nslices must be in [1, %d]", SPAMM_MAX_SLICES);
+    if (!o.mu_rel) return fail(SPAMM_EINVAL, "NULL shift list");
+    for (int j = 0; j < o.nslices; ++j)
+        if (!(o.mu_rel[j] >= 0.0) || std::isinf(o.mu_rel[j])) return fail(SPAMM_EINVAL, "bad shift mu_rel[%d]", j);
+    if (!(o.tau_r >= 0.0) || std::isinf(o.tau_r)) return fail(SPAMM_EINVAL, "tau_r must be finite and >= 0");
+    if (res) std::memset(res, 0, sizeof(*res));
+    const size_t bytes = (size_t)n * ld * sizeof(double);
+    double *buf[6] = {};  // S, T, Wt, M, Y, Z
+    int rc = SPAMM_OK;
+    for (int i = 0; i < 6 && rc == SPAMM_OK; ++i) {
+        const hipError_t e = hipMalloc((void **)&buf[i], bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(SPAMM_ENOMEM, "product representation needs 6 x %zu bytes: %s", bytes, hipGetErrorString(e));
+        }
+    }
+    if (rc == SPAMM_OK) rc = product_rep_body(ctx, s, W, n, ld, o, leaf, buf, res, stream);
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    for (double *b : buf)
+        if (b) (void)hipFree(b);
+    return rc;
+}
+
 int spamm_solve_triples(spamm_ctx *ctx, spamm_solve *s, int which, int32_t *triples, int64_t cap, int64_t *count,
                         void *stream) {
     TRY(enter(ctx));

@@ -141,6 +141,12 @@ hipError_t launch_count_triples(const Geom &g, const int32_t *cnt, int64_t *offs
 hipError_t launch_write_triples(const Geom &g, const int32_t *cnt, const int32_t *kidx, const int64_t *offs,
                                 int32_t *triples, hipStream_t st);
 
+// Dense row-major n x n helpers of the product representation (leading
+// dimension ld): dst = src + mu I; dst = src^T; dst = (src + src^T)/2.
+hipError_t launch_shift_copy(const double *src, double *dst, int64_t n, int64_t ld, double mu, hipStream_t st);
+hipError_t launch_transpose_dense(const double *src, double *dst, int64_t n, int64_t ld, hipStream_t st);
+hipError_t launch_sym_part(const double *src, double *dst, int64_t n, int64_t ld, hipStream_t st);
+
 // Batched stages over a product table.
 hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st);
 // Longest-first job list for leaf tiles of size `leaf` and element size `esz` bytes.

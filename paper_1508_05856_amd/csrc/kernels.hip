@@ -8,6 +8,7 @@
 // squared norms, leaves first (P x P, P = 2^L >= nb), then each parent level.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "device.h"
@@ -772,6 +773,59 @@ __global__ __launch_bounds__(256) void k_sqrt(const double *__restrict__ q, doub
 hipError_t launch_norms_out(const Geom &g, const double *q, double *out, hipStream_t st) {
     const int64_t m = pyr_len(g.P);
     hipLaunchKernelGGL(k_sqrt, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, q, out, m);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dense row-major helpers of the product representation (32 x 32 blocks
+// through LDS for the transposed reads).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_shift_copy(const double *__restrict__ src, double *__restrict__ dst,
+                                                    int64_t n, int64_t ld, double mu) {
+    const int64_t r = blockIdx.y;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
+        double v = src[r * ld + c];
+        if (r == c) v += mu;
+        dst[r * ld + c] = v;
+    }
+}
+
+// mode 0: dst = src^T; mode 1: dst = (src + src^T)/2 (each pair summed in the
+// order src_ij + src_ji, which is commutative, so dst is exactly symmetric)
+__global__ __launch_bounds__(256) void k_transpose_sym(const double *__restrict__ src, double *__restrict__ dst,
+                                                       int64_t n, int64_t ld, int mode) {
+    __shared__ double tileT[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    for (int m = 0; m < 32; m += 8) {  // block (c0, r0) of src, stored transposed
+        const int64_t r = c0 + ty + m, c = r0 + tx;
+        tileT[tx][ty + m] = (r < n && c < n) ? src[r * ld + c] : 0.0;
+    }
+    __syncthreads();
+    for (int m = 0; m < 32; m += 8) {
+        const int64_t r = r0 + ty + m, c = c0 + tx;
+        if (r < n && c < n) {
+            const double t = tileT[ty + m][tx];  // src[c][r]
+            dst[r * ld + c] = mode == 0 ? t : 0.5 * (src[r * ld + c] + t);
+        }
+    }
+}
+
+hipError_t launch_shift_copy(const double *src, double *dst, int64_t n, int64_t ld, double mu, hipStream_t st) {
+    const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 64);
+    hipLaunchKernelGGL(k_shift_copy, dim3(gx, (unsigned)n), dim3(256), 0, st, src, dst, n, ld, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_dense(const double *src, double *dst, int64_t n, int64_t ld, hipStream_t st) {
+    const unsigned nbk = (unsigned)((n + 31) / 32);
+    hipLaunchKernelGGL(k_transpose_sym, dim3(nbk, nbk), dim3(256), 0, st, src, dst, n, ld, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_part(const double *src, double *dst, int64_t n, int64_t ld, hipStream_t st) {
+    const unsigned nbk = (unsigned)((n + 31) / 32);
+    hipLaunchKernelGGL(k_transpose_sym, dim3(nbk, nbk), dim3(256), 0, st, src, dst, n, ld, 1);
     return hipGetLastError();
 }
 

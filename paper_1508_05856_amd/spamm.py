@@ -28,7 +28,8 @@ STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", STAGNATED: "STAGNATED"
 EXPORTS = ("spamm_create", "spamm_destroy", "spamm_last_error", "spamm_pyramid_len", "spamm_norms",
            "spamm_multiply", "ns_sqrt", "spamm_ns_history", "spamm_solve_footprint", "spamm_solve_begin",
            "spamm_solve_step", "spamm_solve_poll", "spamm_solve_finish", "spamm_set_graphs", "spamm_profile_enable",
-           "spamm_profile_read", "spamm_profile_reset", "spamm_solve_triples")
+           "spamm_profile_read", "spamm_profile_reset", "spamm_solve_triples", "spamm_product_rep")
+MAX_SLICES = 16
 KIND_GEMM, KIND_CULL, KIND_PYRAMID = 0, 1, 2
 
 
@@ -47,6 +48,17 @@ class NsOpts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("prec", ctypes.c_int), ("tau_s", ctypes.c_double),
                 ("mu_rel", ctypes.c_double), ("stagnation_stop", ctypes.c_int), ("damped", ctypes.c_int),
                 ("single", ctypes.c_int)]
+
+
+class ProdRepOpts(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int), ("prec", ctypes.c_int), ("nslices", ctypes.c_int),
+                ("mu_rel", ctypes.POINTER(ctypes.c_double)), ("tau_slice", ctypes.c_double),
+                ("tau_s_slice", ctypes.c_double), ("tau_r", ctypes.c_double), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("stagnation_stop", ctypes.c_int), ("damped", ctypes.c_int)]
+
+
+class ProdRepResult(ctypes.Structure):
+    _fields_ = [("nslices_done", ctypes.c_int), ("status", ctypes.c_int * 16), ("iterations", ctypes.c_int * 16)]
 
 
 class NsResult(ctypes.Structure):
@@ -89,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.spamm_solve_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(NsResult)]
         lib.spamm_solve_finish.argtypes = [vp, vp, vp, vp, i64, vp]
         lib.spamm_solve_triples.argtypes = [vp, vp, ctypes.c_int, vp, i64, ctypes.POINTER(ctypes.c_int64), vp]
+        lib.spamm_product_rep.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(ProdRepOpts),
+                                          ctypes.POINTER(ProdRepResult), vp]
         lib.spamm_profile_enable.argtypes = [vp, ctypes.c_int]
         lib.spamm_set_graphs.argtypes = [vp, ctypes.c_int]
         lib.spamm_set_graphs.restype = ctypes.c_int
@@ -212,6 +226,30 @@ class Context:
         if status < 0:
             info["error"] = self.lib.spamm_last_error().decode()
         return Y, Z, info
+
+    def product_rep(self, s: torch.Tensor, mu_rel, tau_slice: float, tau_r: float, tol: float, maxit: int,
+                    leaf: int = 32, prec="f64", tau_s_slice: float = -1.0, stagnation_stop: bool = True,
+                    damped: bool = False, W: torch.Tensor | None = None, raise_on_error: bool = True):
+        """Inverse factor W (W^T (s + mu_rel[-1] c0 I) W ~ I) as a product of
+        regularised slices.  Returns (W, info dict with per-slice status and
+        update counts)."""
+        ps, ld = _mat(s, "s")
+        n = s.shape[0]
+        W = torch.empty_like(s) if W is None else W
+        pw, ldw = _mat(W, "W")
+        if ldw != ld:
+            raise ValueError("W must share s's leading dimension")
+        mu = (ctypes.c_double * len(mu_rel))(*[float(m) for m in mu_rel])
+        opts = ProdRepOpts(leaf, _PREC[prec] if isinstance(prec, str) else int(prec), len(mu_rel), mu,
+                           float(tau_slice), float(tau_s_slice), float(tau_r), float(tol), int(maxit),
+                           int(bool(stagnation_stop)), int(bool(damped)))
+        res = ProdRepResult()
+        status = self.lib.spamm_product_rep(self.handle, ps, pw, n, ld, ctypes.byref(opts), ctypes.byref(res),
+                                            _stream_ptr(s.device))
+        if status < 0 and raise_on_error:
+            _check(status)
+        k = res.nslices_done
+        return W, dict(status=status, statuses=list(res.status[:k]), iterations=list(res.iterations[:k]))
 
     # -- step API (batched and served solves) --------------------------------
     def footprint(self, n: int, leaf: int, prec="f64", maxit: int = 40, single: bool = False) -> int:
