@@ -229,7 +229,7 @@ TableSizes table_sizes(const std::vector<ProdDesc> &prods) {
         z.total_pyr2 += d.P > 32 ? 1 : 0;
         z.max_nb = std::max(z.max_nb, d.nb);
     }
-    z.hist_blocks = z.total_tiles <= 16384 ? 0 : std::min(1024, (z.total_tiles + 4095) / 4096);
+    z.hist_blocks = z.total_tiles <= PLAN_SMALL_MAX ? 0 : std::min(1024, (z.total_tiles + 4095) / 4096);
     return z;
 }
 

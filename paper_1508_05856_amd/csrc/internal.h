@@ -86,7 +86,8 @@ struct ProdDesc {
     const SolveState *state;            // null: always runs, parity 0
 };
 
-constexpr int NBUCKET = 64;  // longest-first buckets of the large-table work-list sort
+constexpr int NBUCKET = 64;          // longest-first buckets of the large-table work-list sort
+constexpr int PLAN_SMALL_MAX = 16384;  // tables up to this many tiles are sorted by one workgroup
 
 // One output tile of one product, with every pointer already resolved for the
 // current parity, so a leaf-product workgroup starts with a single load.

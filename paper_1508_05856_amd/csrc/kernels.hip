@@ -408,6 +408,11 @@ __device__ inline Job make_job(const ProdDesc &d, int t, int cnt, int b, int esz
     return J;
 }
 
+// Small tables (<= PLAN_ITEMS * 1024 tiles, the tables without hist_blocks):
+// every thread loads its items once, with independent loads, and keeps them
+// in registers for the histogram and the scatter.
+constexpr int PLAN_ITEMS = PLAN_SMALL_MAX / 1024;
+
 __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict__ prods,
                                                      const int32_t *__restrict__ tile_pre,
                                                      const int32_t *__restrict__ morton, int nprod, int max_nb,
@@ -415,12 +420,22 @@ __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict_
     extern __shared__ int hist[];  // max_nb + 1 bins
     const int total = tile_pre[nprod];
     for (int c = threadIdx.x; c <= max_nb; c += 1024) hist[c] = 0;
-    __syncthreads();
-    for (int g = threadIdx.x; g < total; g += 1024) {
-        int p, t;
-        const int c = item_count(prods, tile_pre, morton, nprod, g, p, t);
-        if (c >= 0) atomicAdd(&hist[c], 1);
+    int cnt[PLAN_ITEMS], gid[PLAN_ITEMS];
+#pragma unroll
+    for (int q = 0; q < PLAN_ITEMS; ++q) {
+        const int g = threadIdx.x + q * 1024;
+        cnt[q] = -1;
+        gid[q] = 0;
+        if (g < total) {
+            int p, t;
+            cnt[q] = item_count(prods, tile_pre, morton, nprod, g, p, t);
+            gid[q] = tile_pre[p] + t;
+        }
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PLAN_ITEMS; ++q)
+        if (cnt[q] >= 0) atomicAdd(&hist[cnt[q]], 1);
     __syncthreads();
     if (threadIdx.x == 0) {
         int run = 0;
@@ -432,11 +447,9 @@ __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict_
         *work_count = run;
     }
     __syncthreads();
-    for (int g = threadIdx.x; g < total; g += 1024) {
-        int p, t;
-        const int c = item_count(prods, tile_pre, morton, nprod, g, p, t);
-        if (c >= 0) work[atomicAdd(&hist[c], 1)] = tile_pre[p] + t;
-    }
+#pragma unroll
+    for (int q = 0; q < PLAN_ITEMS; ++q)
+        if (cnt[q] >= 0) work[atomicAdd(&hist[cnt[q]], 1)] = gid[q];
 }
 
 __device__ inline int bucket_of(int c) { return c < NBUCKET - 1 ? c : NBUCKET - 1; }

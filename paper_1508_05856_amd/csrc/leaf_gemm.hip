@@ -69,7 +69,10 @@ struct TileCfg {
     static constexpr int Q = (B >= 32) ? 32 : 16;  // rows/cols of C per wave
     static constexpr int NBLK = Q / 16;            // 16x16 MFMA blocks per wave side
     static constexpr int VEC = Mfma<T>::VEC;       // elements per 16-byte chunk
-    static constexpr int KS = (B == 64) ? 32 : B;  // k extent of one pipeline stage
+    // k extent of one pipeline stage: FP64 stages are half as deep, which
+    // halves the LDS and prefetch registers and raises occupancy (3 waves per
+    // SIMD at b = 64, 2 at b = 32); the MFMA sequence is the same
+    static constexpr int KS = (sizeof(T) == 8 && B >= 32) ? 16 : ((B == 64) ? 32 : B);
     static constexpr int SPT = B / KS;             // stages per retained triple
     // LDS row strides (elements).  A stage (B x KS) is read by fragments
     // A[row + l%16][k + l/16]: a stride of KS + 16 bytes puts the 16 rows and
