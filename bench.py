@@ -67,7 +67,8 @@ def parse():
     p.add_argument("--dump-launches", default=None, help="write per-launch (flops, ms) of the timed steps")
     p.add_argument("--compare-f64", action="store_true", help="also solve in FP64 and report the relative gap")
     p.add_argument("--copy-bytes", type=int, default=1 << 31, help="copy: bytes read (and written) per launch")
-    p.add_argument("--workload", default="gauss4096", choices=["gauss4096", "c3", "batched", "serving", "copy"],
+    p.add_argument("--workload", default="gauss4096",
+                   choices=["gauss4096", "c3", "batched", "serving", "copy", "product"],
                    help="gauss4096: the n=4096 Gaussian Gramian (default); batched: 64 uneven solves "
                         "together; serving: a Poisson request stream through the continuous-batching server")
     p.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -306,6 +307,53 @@ def cpu_baseline_sampled_tiles(s, mu_rel, leaf, tau, info):
                        f"set-up) scaled to the solve's {info['triples_total']} triples")}
 
 
+def run_product(args):
+    """One SpAMM product alone: y (x)_tau z of the n = 4096 Gaussian solve at
+    its tau floor (the operands of its last x product, from an untimed
+    solve), timed over K launches with HIP events on the library's stream."""
+    import torch
+
+    from paper_1508_05856_amd import inputs, spamm
+    cfg = inputs.config_c2(args.tau)
+    ctx = spamm.Context(0)
+    s = torch.from_numpy(cfg["s"]).cuda()
+    Y, Z, _ = ctx.ns_sqrt(s, args.tau, args.tol, args.maxit, leaf=cfg["leaf"], prec=args.prec,
+                          stagnation_stop=True, raise_on_error=False)
+    c = _scale_of(s)
+    y, z = Y / c ** 0.5, Z * c ** 0.5  # the scaled iterates the solve multiplies
+    for _ in range(args.warmup):
+        ctx.spamm_multiply(y, z, args.tau, cfg["leaf"], prec=args.prec)
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st, _ = ctx.spamm_multiply(y, z, args.tau, cfg["leaf"], prec=args.prec)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    g = ctx.profile_read(spamm.KIND_GEMM)
+    ctx.profile(False)
+    achieved = st["flops"] / (float(np.mean(g)) * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.prec]
+    if args.prec == "bf16x3":
+        achieved *= 3.0
+    print(json.dumps({"metric": "SpAMM product y (x)_tau z at the n=4096 Gaussian solve's tau floor",
+                      "value": st["flops"] / dt / 1e12, "unit": "useful TFLOP/s (whole product)", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+                      "higher_is_better": True, "dtype": args.prec, "data": "synthetic",
+                      "config": {"workload": f"product_{cfg['name']}", "retained": st["retained"],
+                                 "possible": st["possible"], "flops": st["flops"]},
+                      "roofline": {"bound": "mfma", "kernel": "k_leaf_gemm", "achieved": achieved, "peak": peak,
+                                   "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                                   "avg_launch_ms": float(np.mean(g))}}), flush=True)
+    ctx.close()
+
+
+def _scale_of(s):
+    """Gershgorin bound max_j sum_i |s_ij| (the scale the solve divides by)."""
+    return float(s.abs().sum(0).max())
+
+
 def run_copy(args):
     """A plain elementwise device copy of known size (y = -x over FP64), the
     reference that scales hardware read/write byte counters to bytes."""
@@ -342,6 +390,9 @@ def main():
         return
     if args.workload == "copy":
         run_copy(args)
+        return
+    if args.workload == "product":
+        run_product(args)
         return
 
     import torch
