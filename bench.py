@@ -68,7 +68,7 @@ def parse():
     p.add_argument("--compare-f64", action="store_true", help="also solve in FP64 and report the relative gap")
     p.add_argument("--copy-bytes", type=int, default=1 << 31, help="copy: bytes read (and written) per launch")
     p.add_argument("--workload", default="gauss4096",
-                   choices=["gauss4096", "c3", "batched", "serving", "copy", "product"],
+                   choices=["gauss4096", "c3", "batched", "serving", "copy", "product", "norms"],
                    help="gauss4096: the n=4096 Gaussian Gramian (default); batched: 64 uneven solves "
                         "together; serving: a Poisson request stream through the continuous-batching server")
     p.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -354,6 +354,40 @@ def _scale_of(s):
     return float(s.abs().sum(0).max())
 
 
+def run_norms(args):
+    """The norm pass alone: spamm_norms of the n = 32768 Gaussian Gramian
+    (8 GiB FP64, leaf 64), HBM-bound; algorithmic bytes = one read of s."""
+    import torch
+
+    from paper_1508_05856_amd import inputs, spamm
+    cfg = inputs.config_c3_spec()
+    n = cfg["n"]
+    s = inputs.gramian_device(inputs.gauss_positions(cfg["m"], cfg["h"], 0.1, 0, n), "cuda")
+    ctx = spamm.Context(0)
+    for _ in range(args.warmup):
+        ctx.spamm_norms(s, cfg["leaf"], want_root=False)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[2 * k].record()
+        ctx.spamm_norms(s, cfg["leaf"], want_root=False)
+        ev[2 * k + 1].record()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ms = float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]))
+    nbytes = float(n) * n * 8
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    print(json.dumps({"metric": "norm pyramid of one operand (the norm pass)", "value": nbytes / dt / 1e9,
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": dt * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"norms_{cfg['name']}", "n": n, "leaf": cfg["leaf"]},
+                      "roofline": {"bound": "hbm", "kernel": "k_leaf_norms", "achieved": gbs, "peak": 8000.0,
+                                   "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None,
+                                   "avg_call_ms": ms}}), flush=True)
+    ctx.close()
+
+
 def run_copy(args):
     """A plain elementwise device copy of known size (y = -x over FP64), the
     reference that scales hardware read/write byte counters to bytes."""
@@ -393,6 +427,9 @@ def main():
         return
     if args.workload == "product":
         run_product(args)
+        return
+    if args.workload == "norms":
+        run_norms(args)
         return
 
     import torch

@@ -752,12 +752,11 @@ int spamm_norms(spamm_ctx *ctx, const double *A, int64_t n, int64_t ld, int leaf
     TRY(enter(ctx));
     hipStream_t st = (hipStream_t)stream;
     const Geom g = make_geom(n, leaf);
-    TRY(ensure(ctx, S_T0, (size_t)g.nb * g.nb * g.b * g.b * sizeof(double)));
     TRY(ensure(ctx, S_Q0, (size_t)pyr_len(g.P) * sizeof(double)));
     TRY(ensure(ctx, S_N0, 2 * (size_t)g.nb * g.nb * sizeof(double)));
     double *q = slot_ptr<double>(ctx, S_Q0), *nrm = slot_ptr<double>(ctx, S_N0);
     HIPCHK(hipMemsetAsync(q, 0, (size_t)g.P * g.P * sizeof(double), st));  // virtual blocks read as 0
-    HIPCHK(launch_ingest(P_F64, A, ld, 0.0, 1.0, g, ctx->buf[S_T0], q, st));
+    HIPCHK(launch_leaf_norms(A, ld, g, q, st));
     TIMED(K_PYR, launch_pyramid(g, q, nrm, q, nrm, 1, st));
     HIPCHK(launch_norms_out(g, q, pyramid, st));
     if (root_norm_host) {

@@ -130,6 +130,8 @@ hipError_t launch_colsum_max(const double *s, int64_t n, int64_t ld, double mu, 
 hipError_t launch_ingest(int prec, const double *s, int64_t ld, double mu, double c, const Geom &g, void *tiles,
                          double *qleaf, hipStream_t st);
 hipError_t launch_identity(int prec, const Geom &g, void *tiles, double *qleaf, hipStream_t st);
+// Leaf squared norms of a row-major FP64 matrix (no tile copy).
+hipError_t launch_leaf_norms(const double *s, int64_t ld, const Geom &g, double *qleaf, hipStream_t st);
 // Pyramid of one or two operands (squared-norm pyramid q; leaf norms nrm,
 // 2*nb*nb doubles: row-major, then transposed).
 hipError_t launch_pyramid(const Geom &g, double *q0, double *nrm0, double *q1, double *nrm1, int nops,

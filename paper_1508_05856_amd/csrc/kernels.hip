@@ -179,6 +179,37 @@ __global__ __launch_bounds__(256) void k_ingest(const double *__restrict__ s, in
     if (threadIdx.x == 0) qleaf[(int64_t)i * g.P + k] = q;
 }
 
+// Leaf squared norms of a row-major FP64 matrix read once, with no tile copy
+// (the norm pass of spamm_norms): one workgroup per leaf, its loads issued
+// together before the sums.
+__global__ __launch_bounds__(256) void k_leaf_norms(const double *__restrict__ s, int64_t ld, Geom g,
+                                                    double *__restrict__ qleaf) {
+    __shared__ double sh[4];
+    const int t = blockIdx.x;
+    const int i = t / g.nb, k = t % g.nb;
+    const int b = g.b, per = b * b / 256;  // 16, 4 or 1 elements per thread
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        v[u] = 0.0;
+        if (u < per) {
+            const int e = threadIdx.x + u * 256, r = e / b, cc = e % b;
+            const int64_t gi = (int64_t)i * b + r, gj = (int64_t)k * b + cc;
+            if (gi < g.n && gj < g.n) v[u] = s[gi * ld + gj];
+        }
+    }
+    double q = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) q += v[u] * v[u];
+    q = block_sum<256>(q, sh);
+    if (threadIdx.x == 0) qleaf[(int64_t)i * g.P + k] = q;
+}
+
+hipError_t launch_leaf_norms(const double *s, int64_t ld, const Geom &g, double *qleaf, hipStream_t st) {
+    hipLaunchKernelGGL(k_leaf_norms, dim3((unsigned)g.nb * g.nb), dim3(256), 0, st, s, ld, g, qleaf);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_identity(Geom g, T *__restrict__ tiles, double *__restrict__ qleaf) {
     const int t = blockIdx.x;

@@ -162,14 +162,15 @@ class Context:
     def pyramid_len(self, n: int, leaf: int) -> int:
         return int(self.lib.spamm_pyramid_len(n, leaf))
 
-    def spamm_norms(self, A: torch.Tensor, leaf: int) -> tuple[torch.Tensor, float]:
+    def spamm_norms(self, A: torch.Tensor, leaf: int, want_root: bool = True) -> tuple[torch.Tensor, float | None]:
+        """Norm pyramid of A; the root norm (which synchronises) only if want_root."""
         pa, ld = _mat(A, "A")
         n = A.shape[0]
         out = torch.empty(self.pyramid_len(n, leaf), dtype=torch.float64, device=A.device)
         root = ctypes.c_double(0.0)
-        _check(self.lib.spamm_norms(self.handle, pa, n, ld, leaf, out.data_ptr(), ctypes.byref(root),
-                                    _stream_ptr(A.device)))
-        return out, root.value
+        _check(self.lib.spamm_norms(self.handle, pa, n, ld, leaf, out.data_ptr(),
+                                    ctypes.byref(root) if want_root else None, _stream_ptr(A.device)))
+        return out, (root.value if want_root else None)
 
     def spamm_multiply(self, A: torch.Tensor, B: torch.Tensor, tau: float, leaf: int, prec="f64",
                        C: torch.Tensor | None = None, triples: bool = False, cap: int | None = None):

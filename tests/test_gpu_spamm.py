@@ -73,6 +73,19 @@ def test_norm_pyramid(ctx, n, leaf):
     assert root == pytest.approx(levels[-1][0, 0], rel=1e-14)
 
 
+@pytest.mark.parametrize("n,ld,leaf", [(300, 320, 32), (1000, 1003, 64), (77, 90, 16)])
+def test_norm_pyramid_strided(ctx, n, ld, leaf):
+    """A row-major view with ld > n: only the n x n part enters the norms."""
+    a = decaying(n, seed=n + 1)
+    big = np.full((n, ld), 1e30)
+    big[:, :n] = a
+    view = dev(big)[:, :n]
+    pyr, root = ctx.spamm_norms(view, leaf)
+    levels = oracle.norms(a, leaf)
+    np.testing.assert_allclose(host(pyr), np.concatenate([lv.ravel() for lv in levels]), rtol=1e-14, atol=0)
+    assert root == pytest.approx(levels[-1][0, 0], rel=1e-14)
+
+
 # ---------------------------------------------------------------------------
 # products
 # ---------------------------------------------------------------------------
