@@ -533,37 +533,36 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
 // One Newton-Schulz iteration of every running solve of a plan.
 int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
     const int kp = kernel_prec(p->prec);
-    const int esz = (int)elt_size(p->prec);
     if (p->single) {
         // zt = z_k^T; y_k = s' (x)_{tau_s} z_k; x_k = zt (x)_tau y_k (+ stop test,
         // map); z_{k+1} = z_k (x)_tau h_k
         HIPCHK(launch_transpose_tab(kp, p->tt, p->leaf, st));
         TIMED(K_PYR, launch_pyramid_tab(p->tt, st));
         TIMED(K_CULL, launch_cull_tab(p->ty, st));
-        HIPCHK(launch_plan_tab(p->ty, p->leaf, esz, st));
+        HIPCHK(launch_plan_tab(p->ty, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->ty, st));
         TIMED(K_PYR, launch_pyramid_tab(p->ty, st));
         TIMED(K_CULL, launch_cull_tab(p->tx, st));
-        HIPCHK(launch_plan_tab(p->tx, p->leaf, esz, st));
+        HIPCHK(launch_plan_tab(p->tx, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
         HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
         if (p->damped) HIPCHK(launch_ns_map(kp, p->tx, p->leaf, st));
         TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
         TIMED(K_CULL, launch_cull_tab(p->tz, st));
-        HIPCHK(launch_plan_tab(p->tz, p->leaf, esz, st));
+        HIPCHK(launch_plan_tab(p->tz, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tz, st));
         TIMED(K_PYR, launch_pyramid_tab(p->tz, st));
         HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
         return SPAMM_OK;
     }
     TIMED(K_CULL, launch_cull_tab(p->tx, st));
-    HIPCHK(launch_plan_tab(p->tx, p->leaf, (int)elt_size(p->prec), st));
+    HIPCHK(launch_plan_tab(p->tx, p->leaf, gemm_prec(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
     HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
     if (p->damped) HIPCHK(launch_ns_map(kp, p->tx, p->leaf, st));
     TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
     TIMED(K_CULL, launch_cull_tab(p->tyz, st));
-    HIPCHK(launch_plan_tab(p->tyz, p->leaf, (int)elt_size(p->prec), st));
+    HIPCHK(launch_plan_tab(p->tyz, p->leaf, gemm_prec(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tyz, st));
     TIMED(K_PYR, launch_pyramid_tab(p->tyz, st));
     HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
@@ -827,7 +826,7 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     image.resize(c.off);
     HIPCHK(hipMemcpyAsync(ctx->buf[S_TAB], image.data(), image.size(), hipMemcpyHostToDevice, st));
     TIMED(K_CULL, launch_cull_tab(t, st));
-    HIPCHK(launch_plan_tab(t, leaf, (int)elt_size(prec), st));
+    HIPCHK(launch_plan_tab(t, leaf, gemm_prec(prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(prec), leaf, t, st));
     HIPCHK(launch_egress(kp, g, ctx->buf[S_T2], C, ld, 1.0, 0, st));
     int status = SPAMM_OK;

@@ -88,6 +88,10 @@ struct ProdDesc {
 
 constexpr int NBUCKET = 64;          // longest-first buckets of the large-table work-list sort
 constexpr int PLAN_SMALL_MAX = 16384;  // tables up to this many tiles are sorted by one workgroup
+// BF16x3 leaf products: consecutive jobs of the longest-first order run in
+// groups of this many on one XCD (workgroup w runs on XCD w mod 8), so
+// neighbouring tiles share that XCD's L2.
+constexpr int BF3_XCD_RUN = 64;
 
 // One output tile of one product, with every pointer already resolved for the
 // current parity, so a leaf-product workgroup starts with a single load.
@@ -153,7 +157,7 @@ hipError_t launch_sym_part(const double *src, double *dst, int64_t n, int64_t ld
 // Batched stages over a product table.
 hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st);
 // Longest-first job list for leaf tiles of size `leaf` and element size `esz` bytes.
-hipError_t launch_plan_tab(const ProdTable &t, int leaf, int esz, hipStream_t st);
+hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st);
 hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t st);
 hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st);  // pyramid of each product's C
 // Per solve: r_k, t_k, |R| records and the stop decision.

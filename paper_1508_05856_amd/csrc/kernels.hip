@@ -554,22 +554,38 @@ __global__ __launch_bounds__(256) void k_plan_scatter(const ProdDesc *__restrict
     }
 }
 
-// Expands the sorted tile ids into job records, one thread per entry.
+// Expands the sorted tile ids into job records, one thread per entry.  With
+// run > 1, each window of 8*run consecutive entries is transposed so that
+// entries q*run .. q*run+run-1 of the window land on workgroups that run on
+// XCD q (workgroup w runs on XCD w mod 8): the window's order in time barely
+// changes, and neighbouring tiles meet in one L2.  The partial last window
+// keeps its order.
 __global__ __launch_bounds__(256) void k_make_jobs(const ProdDesc *__restrict__ prods,
                                                    const int32_t *__restrict__ tile_pre, int nprod,
                                                    const int32_t *__restrict__ work,
-                                                   const int32_t *__restrict__ work_count, int b, int esz,
+                                                   const int32_t *__restrict__ work_count, int b, int esz, int run,
                                                    Job *__restrict__ jobs) {
     const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= *work_count) return;
+    const int count = *work_count;
+    if (idx >= count) return;
     const int gid = work[idx];
     const int p = find_slot(tile_pre, nprod, gid);
     const int t = gid - tile_pre[p];
     const ProdDesc &d = prods[p];
-    jobs[idx] = make_job(d, t, d.cnt[t], b, esz);
+    int w = idx;
+    if (run > 1) {
+        const int W = 8 * run;
+        if (idx < count / W * W) {
+            const int q = idx % W;
+            w = idx - q + (q % run) * 8 + q / run;
+        }
+    }
+    jobs[w] = make_job(d, t, d.cnt[t], b, esz);
 }
 
-hipError_t launch_plan_tab(const ProdTable &t, int leaf, int esz, hipStream_t st) {
+hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
+    const int esz = gprec == P_F64 ? 8 : 4;
+    const int run = gprec == P_BF16X3 ? BF3_XCD_RUN : 1;
     if (t.hist_blocks == 0) {
         hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), (t.max_nb + 1) * sizeof(int), st, t.prods, t.tile_pre,
                            t.morton, t.nprod, t.max_nb, t.work, t.work_count);
@@ -581,7 +597,7 @@ hipError_t launch_plan_tab(const ProdTable &t, int leaf, int esz, hipStream_t st
                            t.nprod, t.hist_blocks, t.hist, t.work);
     }
     hipLaunchKernelGGL(k_make_jobs, dim3((t.total_tiles + 255) / 256), dim3(256), 0, st, t.prods, t.tile_pre,
-                       t.nprod, t.work, t.work_count, leaf, esz, t.jobs);
+                       t.nprod, t.work, t.work_count, leaf, esz, run, t.jobs);
     return hipGetLastError();
 }
 

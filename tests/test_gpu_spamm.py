@@ -153,7 +153,7 @@ def test_multiply_f32_error_vs_oracle(ctx):
     assert err < 1e-6
 
 
-@pytest.mark.parametrize("n,leaf", [(500, 32), (640, 64), (64, 64)])
+@pytest.mark.parametrize("n,leaf", [(500, 32), (640, 64), (64, 64), (1600, 32), (1630, 64)])
 def test_multiply_bf16x3_error_vs_oracle(ctx, n, leaf):
     """BF16x3 leaves: operands are stored in FP32, so the cull sees the FP32
     values and R must equal the oracle's R on the FP32-rounded inputs.  Each
@@ -162,7 +162,9 @@ def test_multiply_bf16x3_error_vs_oracle(ctx, n, leaf):
     plus FP32 accumulation; the bound used is 2^-13 sum_R |A_ik||B_kj|
     elementwise (the oracle's SpAMM of |A|, |B| has the same norms, hence the
     same R).  A single bf16 product would be ~2^-9 off, so the Frobenius error
-    must also be far below that."""
+    must also be far below that.  The two larger cases have 2500 and 676
+    tiles, so the BF16x3 job order (windows of 512 jobs spread over the XCDs)
+    has full windows and a ragged last one."""
     tau = 1e-6
     a = decaying(n, seed=17, rate=0.05).astype(np.float32).astype(np.float64)
     b = decaying(n, seed=18, rate=0.05).astype(np.float32).astype(np.float64)
