@@ -309,15 +309,16 @@ def cpu_baseline_sampled_tiles(s, mu_rel, leaf, tau, info):
 
 def run_product(args):
     """One SpAMM product alone: y (x)_tau z of the n = 4096 Gaussian solve at
-    its tau floor (the operands of its last x product, from an untimed
-    solve), timed over K launches with HIP events on the library's stream."""
+    its tau floor (the operands of its last x product, from an untimed FP64
+    solve, so every leaf precision multiplies the same operands), timed over K
+    launches with HIP events on the library's stream."""
     import torch
 
     from paper_1508_05856_amd import inputs, spamm
     cfg = inputs.config_c2(args.tau)
     ctx = spamm.Context(0)
     s = torch.from_numpy(cfg["s"]).cuda()
-    Y, Z, _ = ctx.ns_sqrt(s, args.tau, args.tol, args.maxit, leaf=cfg["leaf"], prec=args.prec,
+    Y, Z, _ = ctx.ns_sqrt(s, args.tau, args.tol, args.maxit, leaf=cfg["leaf"], prec="f64",
                           stagnation_stop=True, raise_on_error=False)
     c = _scale_of(s)
     y, z = Y / c ** 0.5, Z * c ** 0.5  # the scaled iterates the solve multiplies
@@ -343,7 +344,9 @@ def run_product(args):
                       "higher_is_better": True, "dtype": args.prec, "data": "synthetic",
                       "config": {"workload": f"product_{cfg['name']}", "retained": st["retained"],
                                  "possible": st["possible"], "flops": st["flops"]},
-                      "roofline": {"bound": "mfma", "kernel": "k_leaf_gemm", "achieved": achieved, "peak": peak,
+                      "roofline": {"bound": "mfma",
+                                   "kernel": "k_leaf_gemm_bf3" if args.prec == "bf16x3" else "k_leaf_gemm",
+                                   "achieved": achieved, "peak": peak,
                                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                                    "avg_launch_ms": float(np.mean(g))}}), flush=True)
     ctx.close()
