@@ -259,6 +259,11 @@ def run_serving(args):
     statuses = [res.info["status"] for res, _ in results]
     # a request whose solve diverged is answered (with its status) but is not a solve
     nvalid = sum(1 for st in statuses if st >= 0)
+    div_by = {}
+    for (res, r) in results:
+        if res.info["status"] < 0:
+            key = f'{r["kind"]} tau={r["tau"]:g}'
+            div_by[key] = div_by.get(key, 0) + 1
     line = {
         "metric": "NS sqrt serving: solves/sec and p50/p99 latency under Poisson arrivals",
         "value": nvalid / t_end, "unit": "solves/s", "n_gpus": 1, "steps": len(results), "warmup": 2,
@@ -266,7 +271,7 @@ def run_serving(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {
             "workload": f"serving_poisson_{args.rate:g}rps_{args.duration:g}s_n512-{args.nmax}",
-            "requests": len(reqs), "failed": failed, "valid_solves": nvalid,
+            "requests": len(reqs), "failed": failed, "valid_solves": nvalid, "diverged_by": div_by,
             "answered_per_s": len(results) / t_end, "offered_rate": args.rate, "duration_s": args.duration,
             "makespan_s": t_end, "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
