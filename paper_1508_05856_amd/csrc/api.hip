@@ -569,8 +569,6 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
     return SPAMM_OK;
 }
 
-// Arena layout of one solve; returns its size.  With s non-null, also sets
-// the solve's pointers into s->mem.
 // Captures one iteration of a plan on the context's graph stream.
 int capture_iteration(spamm_ctx *ctx, Plan *p) {
     hipStream_t st = ctx->gstream;
@@ -594,6 +592,8 @@ int capture_iteration(spamm_ctx *ctx, Plan *p) {
     return SPAMM_OK;
 }
 
+// Arena layout of one solve; returns its size.  With s non-null, also sets
+// the solve's pointers into s->mem.
 size_t solve_bytes(const Geom &g, int prec, int maxit, int single, spamm_solve *s) {
     Carve c{s ? s->mem : nullptr, 0};
     const size_t tiles = (size_t)g.nb * g.nb * g.b * g.b * elt_size(prec);

@@ -86,6 +86,9 @@ class Server:
             return req.future
         req.t_submit = time.perf_counter()
         with self._lock:
+            if self._stop:
+                req.future.set_exception(RuntimeError("server is closed"))
+                return req.future
             self._pending.append(req)
             self.pending_bytes += s.numel() * s.element_size()
             self.stats["max_pending"] = max(self.stats["max_pending"], len(self._pending))

@@ -103,3 +103,14 @@ def test_admission_by_footprint(solo_results):
     for r, i in zip(res, (4, 6)):
         np.testing.assert_array_equal(r.Y.cpu().numpy(), solo_results[i][0])
         np.testing.assert_array_equal(r.Z.cpu().numpy(), solo_results[i][1])
+
+
+def test_submit_after_close_fails():
+    from paper_1508_05856_amd import serve
+    srv = serve.Server(0, iters_per_step=2)
+    f = srv.submit(mat("kms", 128, 0.7, 0), 1e-6, 1e-8, leaf=32)
+    assert f.result(timeout=60).info["status"] >= 0
+    srv.close()
+    late = srv.submit(mat("kms", 128, 0.7, 0), 1e-6, 1e-8, leaf=32)
+    with pytest.raises(RuntimeError):
+        late.result(timeout=1)
