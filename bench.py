@@ -61,6 +61,7 @@ def parse():
     p.add_argument("--tol", type=float, default=None)
     p.add_argument("--maxit", type=int, default=40)
     p.add_argument("--literal-stop", action="store_true", help="disable the stagnation stop")
+    p.add_argument("--stagnation", action="store_true", help="c1: use the stagnation stop (default: literal)")
     p.add_argument("--damped", action="store_true", help="the damped map (alpha(t), eps(t) of the trace error)")
     p.add_argument("--cpu-sample-iters", type=int, default=8)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -68,7 +69,7 @@ def parse():
     p.add_argument("--compare-f64", action="store_true", help="also solve in FP64 and report the relative gap")
     p.add_argument("--copy-bytes", type=int, default=1 << 31, help="copy: bytes read (and written) per launch")
     p.add_argument("--workload", default="gauss4096",
-                   choices=["gauss4096", "c3", "batched", "serving", "copy", "product", "norms"],
+                   choices=["gauss4096", "c1", "c3", "batched", "serving", "copy", "product", "norms"],
                    help="gauss4096: the n=4096 Gaussian Gramian (default); batched: 64 uneven solves "
                         "together; serving: a Poisson request stream through the continuous-batching server")
     p.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -471,6 +472,18 @@ def main():
         if args.tau_s < 0:
             args.tau_s = cfg["tau_s_rel"] * args.tau
         args.damped = args.damped or cfg["damped"]
+    elif args.workload == "c1":
+        # KMS rho = 0.7, n = 512, leaf 32, stop at tol 1e-10 or 40 updates (the
+        # literal rule unless --stagnation is given): launch-latency bound
+        cfg = inputs.config_c1()
+        s_host = cfg["s"]
+        n, leaf = s_host.shape[0], cfg["leaf"]
+        s = torch.from_numpy(s_host).to(dev)
+        if args.tau_cli is None:
+            args.tau = cfg["tau"]
+        if args.tol_cli is None:
+            args.tol = cfg["tol"]
+        stag = args.stagnation
     else:
         cfg = inputs.config_c2(args.tau)
         s_host = cfg["s"]
@@ -579,6 +592,7 @@ def main():
             "map": "damped" if args.damped else "plain",
             "status": spamm.STATUS_NAMES.get(info["status"], info["status"]),
             "iterations": info["iterations"], "resid_inloop": info["resid"], "resid_exact": resid_exact,
+            "us_per_update": ms_per_step * 1e3 / max(info["iterations"], 1),
             "trace_err": info["trace_err"], "triples_per_solve": info["triples_total"],
             "flops_per_solve": info["flops_total"], "mu_rel": mu_rel, "rel_vs_f64": rel_vs_f64,
         },
