@@ -19,7 +19,13 @@
  *   - Dual-channel coupled Newton-Schulz (Sec. 3.2, eq. "cannonical") with
  *     the map h[x] = (3I - x)/2 (alpha = 1), started from y = s/c, z = I.
  *   - Relative trace error t_k = (n - tr x_k)/n (Sec. 4.2).
- *   - Tikhonov shift s + mu I (Sec. 6).
+ *   - The damped map, alpha(t) and eps(t) driven by the trace error
+ *     (Sec. 4.2, "Mapping").
+ *   - The single-channel instance z_{k+1} = z_k h[z_k^T s z_k]
+ *     (Sec. 3.2, eq. "single").
+ *   - Tikhonov shift s + mu I (Sec. 6), and the product representation of
+ *     the regularised inverse factor by iterative regularisation (Secs. 6.1,
+ *     6.3).
  *
  * Readings taken where the paper is silent or garbled (each is listed in the
  * design notes): the lower block row of eq. "newspamm" is printed twice; the
@@ -33,6 +39,11 @@
  * something other than itself (NumPy norms and products, brute-force culling,
  * the Proposition's bound, eigendecomposition, the KMS closed-form inverse,
  * Higham's sign identity, the scalar spectral recurrence).
+ *
+ * Parity unpinned: the trajectory of the iteration at tau > 0 (its residual
+ * and retained counts step by step) has no printed values in the paper; it is
+ * pinned only through the per-product checks above and the invariants that
+ * hold up to the tau floor.
  */
 #include <math.h>
 #include <stdint.h>
