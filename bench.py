@@ -76,6 +76,8 @@ def parse():
     p.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     p.add_argument("--nmax", type=int, default=16384, help="serving: largest n (log-uniform from 512)")
     p.add_argument("--iters-per-step", type=int, default=4, help="batched: iterations per synchronisation")
+    p.add_argument("--lanes", default="4096", help="serving: comma-separated largest n of each engine lane "
+                   "but the last (each lane has its own stream); empty = one lane")
     a = p.parse_args()
     a.tau_cli, a.tol_cli = a.tau, a.tol
     if a.tau is None:
@@ -194,7 +196,8 @@ def run_serving(args):
 
     reqs = inputs.serving_requests(args.rate, args.duration, seed=0, nmin=512, nmax=args.nmax)
     dev = torch.device("cuda:0")
-    srv = serve.Server(0, iters_per_step=args.iters_per_step)
+    lanes = tuple(int(x) for x in args.lanes.split(",") if x) + (None,)
+    srv = serve.Server(0, iters_per_step=args.iters_per_step, lanes=lanes)
     # warm up kernels and tables on a tiny stream
     for f in [srv.submit(inputs.kms_device(n, 0.7, dev), 1e-6, 1e-8, leaf=64) for n in (512, 1024)]:
         f.result()
@@ -277,6 +280,7 @@ def run_serving(args):
             "makespan_s": t_end, "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
             "tol": 1e-8, "tau_s": "0.01 tau", "stop": "stagnation", "iters_per_step": args.iters_per_step,
+            "lanes": [x if x is not None else "rest" for x in lanes],
             "sizes_n": [int(min(r["n"] for r in reqs)), int(max(r["n"] for r in reqs))],
             "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
             "useful_tflops": sum(res.info["flops_total"] for res, _ in results) / t_end / 1e12,

@@ -1,13 +1,16 @@
 """Continuous-batching server for Newton-Schulz square-root solves on one GPU.
 
-Requests (s, tau, tol, ...) arrive from any thread.  A single engine thread
-admits pending requests as solver slots while their device footprint
-(spamm_solve_footprint) fits the HBM budget, then advances every admitted
-solve by a few iterations per step in shared launches (spamm_solve_step);
-solves that stop leave at the step boundary, their results are written out
-and their memory is released, and newly arrived requests join the next step.
-Each solve's arithmetic does not depend on which others share its launches,
-so a result is the same alone and in any mix.
+Requests (s, tau, tol, ...) arrive from any thread.  Each lane of the server
+is an engine thread with its own library context and HIP stream; a request
+goes to the lane of its size class.  A lane admits pending requests as solver
+slots while the device footprint of everything admitted (spamm_solve_footprint,
+over all lanes) fits the HBM budget, then advances every admitted solve by a
+few iterations per step in shared launches (spamm_solve_step); solves that stop
+leave at the step boundary, their results are written out and their memory is
+released, and newly arrived requests join the next step.  Lanes run on
+separate streams, so small solves need not wait for the steps of large ones.
+Each solve's arithmetic does not depend on which others share its launches or
+its lane, so a result is the same alone and in any mix.
 """
 from __future__ import annotations
 
@@ -38,10 +41,14 @@ class Request:
     t_submit: float = 0.0
     future: Future = field(default_factory=Future)
     footprint: int = 0
+    ready: object = None  # torch.cuda.Event recorded on the submitter's stream after s was written
 
 
 @dataclass
 class Result:
+    """Y and Z are complete when the result is set (the lane synchronised its
+    stream); a caller that hands them to work on another stream and then
+    drops them should call record_stream first, as for any tensor."""
     Y: torch.Tensor
     Z: torch.Tensor
     info: dict
@@ -50,10 +57,25 @@ class Result:
     t_done: float      # time.perf_counter() when the result was ready
 
 
+class _Lane:
+    def __init__(self, server: "Server", device: int, nmax: int | None):
+        self.nmax = nmax  # largest n this lane takes (None: no bound)
+        self.ctx = spamm.Context(device)
+        self.stream = torch.cuda.Stream(device)  # default priority
+        self.pending: collections.deque[Request] = collections.deque()
+        self.active: list[tuple[Request, spamm.Solve, float]] = []
+        self.thread = threading.Thread(target=server._loop, args=(self,), name="spamm-engine", daemon=True)
+
+
 class Server:
     def __init__(self, device: int = 0, hbm_budget: int | None = None, iters_per_step: int = 2,
-                 max_active: int = 512, autostart: bool = True):
-        self.ctx = spamm.Context(device)
+                 max_active: int = 512, autostart: bool = True, lanes: tuple = (None,)):
+        """lanes: the largest n of each lane in increasing order, the last one
+        None (no bound); the default is one lane for every size."""
+        lanes = tuple(lanes)
+        if not lanes or lanes[-1] is not None or any(a is None for a in lanes[:-1]) or any(
+                a >= b for a, b in zip(lanes[:-2], lanes[1:-1])):
+            raise ValueError("lanes must be increasing size bounds ending with None")
         self.device = torch.device("cuda", device)
         if hbm_budget is None:
             free, _total = torch.cuda.mem_get_info(device)
@@ -61,21 +83,21 @@ class Server:
         self.hbm_budget = hbm_budget
         self.iters_per_step = iters_per_step
         self.max_active = max_active
-        self._pending: collections.deque[Request] = collections.deque()
         self._lock = threading.Condition()
         self._stop = False
-        self._active: list[tuple[Request, spamm.Solve, float]] = []
+        self._lanes = [_Lane(self, device, nmax) for nmax in lanes]
+        self.ctx = self._lanes[0].ctx  # for footprint queries
         self.in_use = 0
         self.pending_bytes = 0
         self.stats = dict(steps=0, admitted=0, completed=0, failed=0, max_active=0, max_pending=0, peak_bytes=0)
-        self._thread = threading.Thread(target=self._loop, name="spamm-engine", daemon=True)
         if autostart:
-            self._thread.start()
+            self.start()
 
     def start(self):
-        """Start the engine thread (for a server made with autostart=False)."""
-        if not self._thread.is_alive():
-            self._thread.start()
+        """Start the engine threads (for a server made with autostart=False)."""
+        for lane in self._lanes:
+            if not lane.thread.is_alive():
+                lane.thread.start()
 
     # -- client side ----------------------------------------------------------
     def submit(self, s: torch.Tensor, tau: float, tol: float, **kw) -> Future:
@@ -84,89 +106,111 @@ class Server:
         if req.footprint == 0 or req.footprint > self.hbm_budget:
             req.future.set_exception(ValueError(f"request needs {req.footprint} bytes; budget {self.hbm_budget}"))
             return req.future
+        req.ready = torch.cuda.Event()
+        req.ready.record(torch.cuda.current_stream(s.device))
         req.t_submit = time.perf_counter()
+        lane = next(ln for ln in self._lanes if ln.nmax is None or s.shape[0] <= ln.nmax)
         with self._lock:
             if self._stop:
                 req.future.set_exception(RuntimeError("server is closed"))
                 return req.future
-            self._pending.append(req)
+            lane.pending.append(req)
             self.pending_bytes += s.numel() * s.element_size()
-            self.stats["max_pending"] = max(self.stats["max_pending"], len(self._pending))
-            self._lock.notify()
+            npend = sum(len(ln.pending) for ln in self._lanes)
+            self.stats["max_pending"] = max(self.stats["max_pending"], npend)
+            self._lock.notify_all()
         return req.future
 
     def backlog(self) -> tuple[int, int]:
         """(requests, input bytes) submitted and not yet admitted."""
         with self._lock:
-            return len(self._pending), self.pending_bytes
+            return sum(len(ln.pending) for ln in self._lanes), self.pending_bytes
 
     def close(self):
-        """Finish every submitted request, then stop the engine."""
+        """Finish every submitted request, then stop the engines."""
         self.start()
         with self._lock:
             self._stop = True
-            self._lock.notify()
-        self._thread.join()
-        self.ctx.close()
+            self._lock.notify_all()
+        for lane in self._lanes:
+            lane.thread.join()
+        for lane in self._lanes:
+            lane.ctx.close()
 
-    # -- engine thread --------------------------------------------------------
-    def _admit(self):
+    # -- engine threads -------------------------------------------------------
+    def _admit(self, lane: _Lane) -> bool:
+        """Admit what fits; False when a pending request waits for memory."""
         while True:
             with self._lock:
-                if not self._pending or len(self._active) >= self.max_active:
-                    return
-                req = self._pending[0]
-                if self.in_use + req.footprint > self.hbm_budget and self._active:
-                    return  # wait for memory to free up at a step boundary
-                self._pending.popleft()
+                if not lane.pending or len(lane.active) >= self.max_active:
+                    return True
+                req = lane.pending[0]
+                if self.in_use + req.footprint > self.hbm_budget and self.in_use > 0:
+                    return False  # memory frees up at some lane's step boundary
+                lane.pending.popleft()
                 self.pending_bytes -= req.s.numel() * req.s.element_size()
+                self.in_use += req.footprint  # reserved before the lock is released
+                self.stats["peak_bytes"] = max(self.stats["peak_bytes"], self.in_use)
             t_admit = time.perf_counter()
             try:
-                sv = self.ctx.solve_begin(req.s, req.tau, req.tol, req.maxit, leaf=req.leaf, prec=req.prec,
+                lane.stream.wait_event(req.ready)
+                sv = lane.ctx.solve_begin(req.s, req.tau, req.tol, req.maxit, leaf=req.leaf, prec=req.prec,
                                           tau_s=req.tau_s, mu_rel=req.mu_rel,
                                           stagnation_stop=req.stagnation_stop, damped=req.damped,
                                           single=req.single)
             except Exception as e:  # invalid input or no memory: fail this request only
                 req.s = None
+                self._release(req.footprint)
                 req.future.set_exception(e)
                 continue
-            req.s = None  # the solve holds its own blocked copy of s
-            self.in_use += req.footprint
-            self.stats["peak_bytes"] = max(self.stats["peak_bytes"], self.in_use)
-            self._active.append((req, sv, t_admit))
-            self.stats["admitted"] += 1
+            req.s = None  # the solve holds its own blocked copy of s (begin synchronised its stream)
+            lane.active.append((req, sv, t_admit))
+            with self._lock:
+                self.stats["admitted"] += 1
 
-    def _fail_active(self, err: Exception):
+    def _release(self, nbytes: int):
+        with self._lock:
+            self.in_use -= nbytes
+            self._lock.notify_all()
+
+    def _fail_active(self, lane: _Lane, err: Exception):
         """A shared launch failed: every solve in it fails, and its memory is released."""
-        for req, sv, _ in self._active:
+        for req, sv, _ in lane.active:
             try:
                 sv.finish(want_outputs=False)
             except Exception:
                 pass
-            self.in_use -= req.footprint
+            self._release(req.footprint)
             req.future.set_exception(err)
-            self.stats["failed"] += 1
-        self._active = []
+            with self._lock:
+                self.stats["failed"] += 1
+        lane.active = []
 
-    def _loop(self):
+    def _loop(self, lane: _Lane):
+        torch.cuda.set_stream(lane.stream)  # this thread's library calls go to the lane's stream
         while True:
             with self._lock:
-                while not self._stop and not self._pending and not self._active:
+                while not self._stop and not lane.pending and not lane.active:
                     self._lock.wait()
-                if self._stop and not self._active and not self._pending:
+                if self._stop and not lane.active and not lane.pending:
                     return
-            self._admit()
-            if not self._active:
+            fits = self._admit(lane)
+            if not lane.active:
+                if not fits:
+                    with self._lock:
+                        self._lock.wait(timeout=0.01)
                 continue
-            self.stats["max_active"] = max(self.stats["max_active"], len(self._active))
+            with self._lock:
+                self.stats["max_active"] = max(self.stats["max_active"], sum(len(ln.active) for ln in self._lanes))
             try:
-                self.ctx.solve_step([sv for _, sv, _ in self._active], self.iters_per_step)
+                lane.ctx.solve_step([sv for _, sv, _ in lane.active], self.iters_per_step)
             except Exception as e:
-                self._fail_active(e)
+                self._fail_active(lane, e)
                 continue
-            self.stats["steps"] += 1
+            with self._lock:
+                self.stats["steps"] += 1
             still = []
-            for req, sv, t_admit in self._active:
+            for req, sv, t_admit in lane.active:
                 if not sv.poll()["done"]:
                     still.append((req, sv, t_admit))
                     continue
@@ -176,12 +220,14 @@ class Server:
                 except Exception as e:  # e.g. no memory for the outputs
                     if sv.handle is not None:
                         sv.finish(want_outputs=False)
-                    self.in_use -= req.footprint
+                    self._release(req.footprint)
                     req.future.set_exception(e)
-                    self.stats["failed"] += 1
+                    with self._lock:
+                        self.stats["failed"] += 1
                     continue
-                self.in_use -= req.footprint
+                self._release(req.footprint)
                 now = time.perf_counter()
-                self.stats["completed"] += 1
+                with self._lock:
+                    self.stats["completed"] += 1
                 req.future.set_result(Result(Y, Z, info, now - req.t_submit, t_admit - req.t_submit, now))
-            self._active = still
+            lane.active = still

@@ -48,9 +48,11 @@ def solo_results():
     return out
 
 
-def test_requests_joining_a_running_mix_match_solo(solo_results):
+@pytest.mark.parametrize("lanes", [(None,), (700, None)])
+def test_requests_joining_a_running_mix_match_solo(solo_results, lanes):
+    """One lane, and two lanes (n <= 700 and the rest) on their own streams."""
     from paper_1508_05856_amd import serve
-    srv = serve.Server(0, iters_per_step=1, autostart=False)
+    srv = serve.Server(0, iters_per_step=1, autostart=False, lanes=lanes)
     futs = {}
     for i in range(3):  # queued before the engine starts: admitted together
         kind, n, p, sd, leaf, tau = REQS[i]
