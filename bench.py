@@ -76,7 +76,7 @@ def parse():
     p.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     p.add_argument("--nmax", type=int, default=16384, help="serving: largest n (log-uniform from 512)")
     p.add_argument("--iters-per-step", type=int, default=4, help="batched: iterations per synchronisation")
-    p.add_argument("--lanes", default="4096", help="serving: comma-separated largest n of each engine lane "
+    p.add_argument("--lanes", default="2048,8192", help="serving: comma-separated largest n of each engine lane "
                    "but the last (each lane has its own stream); empty = one lane")
     a = p.parse_args()
     a.tau_cli, a.tol_cli = a.tau, a.tol
