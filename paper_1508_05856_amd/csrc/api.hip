@@ -123,6 +123,10 @@ struct spamm_ctx {
     bool graphs = true;                   // replay captured iterations when not timing launches
     hipStream_t gstream = nullptr;        // stream the graphs are captured on and replayed on
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // further replay streams (default priority), one per plan of a step beyond
+    // the first, so that the plans of one step run concurrently
+    std::vector<hipStream_t> xstream;
+    std::vector<hipEvent_t> xdone;
 };
 
 struct spamm_solve {
@@ -729,6 +733,8 @@ int spamm_destroy(spamm_ctx *ctx) {
     ctx->plans.clear();
     for (hipEvent_t e : ctx->pool) HIPCHK(hipEventDestroy(e));
     if (ctx->gstream) HIPCHK(hipStreamDestroy(ctx->gstream));
+    for (hipStream_t x : ctx->xstream) HIPCHK(hipStreamDestroy(x));
+    for (hipEvent_t e : ctx->xdone) HIPCHK(hipEventDestroy(e));
     if (ctx->ev_in) HIPCHK(hipEventDestroy(ctx->ev_in));
     if (ctx->ev_out) HIPCHK(hipEventDestroy(ctx->ev_out));
     for (int s = 0; s < S_COUNT; ++s)
@@ -951,6 +957,31 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
     return SPAMM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Replay streams for `count` plans: the graph stream, then extra ones.
+int replay_streams(spamm_ctx *ctx, size_t count) {
+    while (ctx->xstream.size() + 1 < count) {
+        hipStream_t x = nullptr;
+        hipEvent_t e = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        const hipError_t er = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (er != hipSuccess) {
+            (void)hipStreamDestroy(x);
+            return fail(SPAMM_EHIP, "event creation failed: %s", hipGetErrorString(er));
+        }
+        ctx->xstream.push_back(x);
+        ctx->xdone.push_back(e);
+    }
+    return SPAMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int iterations, void *stream) {
     TRY(enter(ctx));
     if (count < 0 || (count > 0 && !solves)) return fail(SPAMM_EINVAL, "bad solve list");
@@ -981,29 +1012,37 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
     }
     const bool use_graphs = ctx->graphs && !ctx->prof;
     if (use_graphs) {
-        // the graph stream waits for the caller's stream, runs the step, and
-        // the caller's stream waits for it (the step also blocks the host)
-        HIPCHK(hipEventRecord(ctx->ev_in, st));
-        HIPCHK(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
+        // Plan q replays on its own stream (the graph stream for the first):
+        // the plans touch disjoint solves, so they run concurrently.  Every
+        // replay stream waits for the caller's stream, and the caller's stream
+        // waits for all of them (the step also blocks the host).
         for (Plan *p : plans)
             if (!p->graph_exec) TRY(capture_iteration(ctx, p));
-        for (int it = 0; it < iterations; ++it)
-            for (Plan *p : plans) HIPCHK(hipGraphLaunch(p->graph_exec, ctx->gstream));
+        TRY(replay_streams(ctx, plans.size()));
+        HIPCHK(hipEventRecord(ctx->ev_in, st));
+        for (size_t q = 0; q < plans.size(); ++q) {
+            hipStream_t rq = q == 0 ? ctx->gstream : ctx->xstream[q - 1];
+            HIPCHK(hipStreamWaitEvent(rq, ctx->ev_in, 0));
+            for (int it = 0; it < iterations; ++it) HIPCHK(hipGraphLaunch(plans[q]->graph_exec, rq));
+            HIPCHK(launch_gather_states(plans[q]->solves, plans[q]->nsolve, plans[q]->gather, rq));
+            HIPCHK(hipMemcpyAsync(plans[q]->gather_host, plans[q]->gather, plans[q]->nsolve * sizeof(SolveState),
+                                  hipMemcpyDeviceToHost, rq));
+            hipEvent_t done = q == 0 ? ctx->ev_out : ctx->xdone[q - 1];
+            HIPCHK(hipEventRecord(done, rq));
+            HIPCHK(hipStreamWaitEvent(st, done, 0));
+        }
+        for (size_t q = 0; q < plans.size(); ++q)
+            HIPCHK(hipStreamSynchronize(q == 0 ? ctx->gstream : ctx->xstream[q - 1]));
     } else {
         for (int it = 0; it < iterations; ++it)
             for (Plan *p : plans) TRY(enqueue_iteration(ctx, p, st));
+        for (Plan *p : plans) {
+            HIPCHK(launch_gather_states(p->solves, p->nsolve, p->gather, st));
+            HIPCHK(hipMemcpyAsync(p->gather_host, p->gather, p->nsolve * sizeof(SolveState),
+                                  hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
     }
-    hipStream_t rs = use_graphs ? ctx->gstream : st;
-    for (Plan *p : plans) {
-        HIPCHK(launch_gather_states(p->solves, p->nsolve, p->gather, rs));
-        HIPCHK(hipMemcpyAsync(p->gather_host, p->gather, p->nsolve * sizeof(SolveState), hipMemcpyDeviceToHost,
-                              rs));
-    }
-    if (use_graphs) {
-        HIPCHK(hipEventRecord(ctx->ev_out, rs));
-        HIPCHK(hipStreamWaitEvent(st, ctx->ev_out, 0));
-    }
-    HIPCHK(hipStreamSynchronize(rs));
     int running = 0;
     for (size_t gi = 0; gi < groups.size(); ++gi)
         for (size_t i = 0; i < groups[gi].size(); ++i) {
@@ -1012,6 +1051,8 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
         }
     return running;
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -1066,6 +1107,8 @@ int product_rep_body(spamm_ctx *ctx, const double *s, double *W, int64_t n, int6
 }
 
 }  // namespace
+
+extern "C" {
 
 int spamm_product_rep(spamm_ctx *ctx, const double *s, double *W, int64_t n, int64_t ld,
                       const spamm_prodrep_opts *opts, spamm_prodrep_result *res, void *stream) {

@@ -57,3 +57,17 @@ def test_null_context_is_rejected_without_gpu(lib_path):
     st = lib.spamm_norms(None, None, 16, 16, 16, None, None, None)
     assert st == spamm.EINVAL
     assert b"NULL" in lib.spamm_last_error()
+
+
+def test_library_exports_nothing_else_unmangled(lib_path):
+    """Every defined symbol with C linkage is one the header declares (helpers
+    stay internal)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm is not available")
+    out = subprocess.run([nm, "-D", "--defined-only", lib_path], check=True, capture_output=True, text=True).stdout
+    c_names = {line.split()[-1] for line in out.splitlines()
+               if len(line.split()) == 3 and line.split()[1] == "T" and not line.split()[-1].startswith("_")}
+    assert c_names == set(declared_functions()), sorted(c_names ^ set(declared_functions()))
