@@ -116,3 +116,26 @@ def test_submit_after_close_fails():
     late = srv.submit(mat("kms", 128, 0.7, 0), 1e-6, 1e-8, leaf=32)
     with pytest.raises(RuntimeError):
         late.result(timeout=1)
+
+
+def test_invalid_request_fails_alone(solo_results):
+    """An input the library rejects (not symmetric) fails its own future only."""
+    from paper_1508_05856_amd import serve, spamm
+    srv = serve.Server(0, iters_per_step=2, autostart=False, lanes=(700, None))
+    good = {}
+    for i in (0, 2):
+        kind, n, p, sd, leaf, tau = REQS[i]
+        good[i] = srv.submit(mat(kind, n, p, sd), tau, 1e-8, maxit=40, leaf=leaf, stagnation_stop=True)
+    bad = mat("kms", 320, 0.7, 0)
+    bad[0, 5] += 1.0
+    bad_f = srv.submit(bad, 1e-8, 1e-8, maxit=40, leaf=32, stagnation_stop=True)
+    srv.start()
+    res = {i: f.result(timeout=120) for i, f in good.items()}
+    with pytest.raises(spamm.SpammError):
+        bad_f.result(timeout=120)
+    stats = dict(srv.stats)
+    srv.close()
+    assert stats["completed"] == 2
+    for i, r in res.items():
+        np.testing.assert_array_equal(r.Y.cpu().numpy(), solo_results[i][0])
+        np.testing.assert_array_equal(r.Z.cpu().numpy(), solo_results[i][1])
