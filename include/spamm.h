@@ -163,7 +163,9 @@ typedef struct {
  *   EINVAL.  Y ~ s^{1/2} = sqrt(c) y_k and Z ~ s^{-1/2} = z_k / sqrt(c):
  *   DEVICE outputs with leading dimension ld.  opts: NULL = defaults (leaf 32,
  *   F64, tau_s = tau, no shift, literal stop rule).  res: optional HOST output.
- * Synchronises the stream once per iteration (the stop test) and at the end.
+ * The stop test runs on the device; the host reads the solve's state back once
+ * per step of up to four iterations (iterations after a stop do no work) and
+ * synchronises at the end.
  */
 int ns_sqrt(spamm_ctx *ctx, const double *s, double *Y, double *Z, int64_t n, int64_t ld, double tau,
             double tol, int maxit, const spamm_ns_opts *opts, spamm_ns_result *res, void *stream);
@@ -193,9 +195,12 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
 
 /* Advances every running solve in solves[0..count) by `iterations` (>= 1)
  * iterations: each iteration of all of them is one shared sequence of
- * launches per (precision, leaf) group; the stop tests run on the device.
- * Finished solves in the list are skipped.  Synchronises once.  Returns the
- * number of solves of the list still running, or < 0 on error. */
+ * launches per (precision, leaf, channel) group; the stop tests run on the
+ * device.  The groups run concurrently on streams of the context that start
+ * after the work already on `stream`, and `stream` waits for all of them.
+ * Finished solves in the list are skipped; a solve may appear once.
+ * Synchronises once.  Returns the number of solves of the list still running,
+ * or < 0 on error (EINVAL for a NULL, repeated or foreign solve). */
 int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int iterations, void *stream);
 
 /* Host-side state after the last step: *done = 1 once stopped; res as for
