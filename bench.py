@@ -365,11 +365,18 @@ def run_product(args):
                       "config": {"workload": f"product_{cfg['name']}", "retained": st["retained"],
                                  "possible": st["possible"], "flops": st["flops"]},
                       "roofline": {"bound": "mfma",
-                                   "kernel": "k_leaf_gemm_bf3" if args.prec == "bf16x3" else "k_leaf_gemm",
+                                   "kernel": _gemm_kernel(args.prec, cfg["leaf"]),
                                    "achieved": achieved, "peak": peak,
                                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                                    "avg_launch_ms": float(np.mean(g))}}), flush=True)
     ctx.close()
+
+
+def _gemm_kernel(prec, leaf):
+    """Name of the leaf-product kernel a precision and leaf size run."""
+    if prec == "bf16x3":
+        return "k_leaf_gemm_bf3_quad" if leaf == 64 else "k_leaf_gemm_bf3"
+    return "k_leaf_gemm"
 
 
 def _scale_of(s):
@@ -601,7 +608,7 @@ def main():
             "flops_per_solve": info["flops_total"], "mu_rel": mu_rel, "rel_vs_f64": rel_vs_f64,
         },
         "roofline": {
-            "bound": "mfma", "kernel": "k_leaf_gemm_bf3" if args.prec == "bf16x3" else "k_leaf_gemm", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "bound": "mfma", "kernel": _gemm_kernel(args.prec, leaf), "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": committed_traffic(cfg["name"], args.prec),
             "traffic_unit": "bytes per launch", "useful_tflops": useful,
             "launches": len(gemm_ms), "avg_launch_ms": float(np.mean(gemm_ms)),

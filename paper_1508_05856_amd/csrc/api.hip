@@ -55,6 +55,7 @@ size_t elt_size(int prec) { return prec == SPAMM_F64 ? 8 : 4; }
 int kernel_prec(int prec) { return prec == SPAMM_F64 ? P_F64 : P_F32; }
 int gemm_prec(int prec) { return prec == SPAMM_F64 ? P_F64 : (prec == SPAMM_BF16X3 ? P_BF16X3 : P_F32); }
 constexpr int MAX_NB = 1024;  // the pyramid's two passes cover P <= 1024
+static_assert(MAX_NB <= QUAD_NB_MAX, "the quad kernel's k union covers every supported nb");
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -221,14 +222,15 @@ int validate_common(spamm_ctx *ctx, const void *A, int64_t n, int64_t ld, int le
 
 // ---- product tables ----------------------------------------------------------
 struct TableSizes {
-    int nprod, total_cull, total_tiles, total_pyr, total_pyr2, max_nb, hist_blocks;
+    int nprod, total_cull, total_tiles, total_pyr, total_pyr2, total_quads, max_nb, hist_blocks;
 };
 
 TableSizes table_sizes(const std::vector<ProdDesc> &prods) {
-    TableSizes z{(int)prods.size(), 0, 0, 0, 0, 0, 0};
+    TableSizes z{(int)prods.size(), 0, 0, 0, 0, 0, 0, 0};
     for (const ProdDesc &d : prods) {
         z.total_cull += (d.nb * d.nb + 3) / 4;
         z.total_tiles += d.nb * d.nb;
+        z.total_quads += ((d.nb + 1) / 2) * ((d.nb + 1) / 2);
         z.total_pyr += d.P <= 32 ? 1 : (d.P / 32) * (d.P / 32);
         z.total_pyr2 += d.P > 32 ? 1 : 0;
         z.max_nb = std::max(z.max_nb, d.nb);
@@ -255,13 +257,14 @@ ProdTable layout_table(Carve &c, const std::vector<ProdDesc> &prods, std::vector
     const size_t o_mort = c.off;
     t.morton = c.take<int32_t>(z.total_tiles);
     t.work = c.take<int32_t>(z.total_tiles);
-    t.jobs = c.take<Job>(z.total_tiles);
+    t.jobs = c.take<Job>(4 * (size_t)z.total_quads);  // >= total_tiles
     t.work_count = c.take<int32_t>(1);
     t.hist = c.take<int32_t>((size_t)NBUCKET * std::max(z.hist_blocks, 1));
     t.nprod = z.nprod;
     t.hist_blocks = z.hist_blocks;
     t.total_cull = z.total_cull;
     t.total_tiles = z.total_tiles;
+    t.total_quads = z.total_quads;
     t.total_pyr = z.total_pyr;
     t.total_pyr2 = z.total_pyr2;
     t.max_nb = z.max_nb;

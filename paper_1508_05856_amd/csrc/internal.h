@@ -89,9 +89,16 @@ struct ProdDesc {
 constexpr int NBUCKET = 64;          // longest-first buckets of the large-table work-list sort
 constexpr int PLAN_SMALL_MAX = 16384;  // tables up to this many tiles are sorted by one workgroup
 // BF16x3 leaf products: consecutive jobs of the longest-first order run in
-// groups of this many on one XCD (workgroup w runs on XCD w mod 8), so
+// groups of this many tiles on one XCD (workgroup w runs on XCD w mod 8), so
 // neighbouring tiles share that XCD's L2.
 constexpr int BF3_XCD_RUN = 64;
+
+// BF16x3 products of 64x64 leaves run one workgroup per quad of output tiles
+// (2i..2i+1, 2j..2j+1): the quad's workgroup stages each A_ik and B_kj once
+// for the tiles of the quad that retain k.  The quad kernel keeps the union of
+// the four retained lists in LDS, for at most QUAD_NB_MAX tiles per side.
+constexpr int QUAD_NB_MAX = 1024;
+inline bool quad_tiles(int gprec, int leaf) { return gprec == P_BF16X3 && leaf == 64; }
 
 // One output tile of one product, with every pointer already resolved for the
 // current parity, so a leaf-product workgroup starts with a single load.
@@ -118,12 +125,15 @@ struct ProdTable {
     const int32_t *pyr_pre;   // nprod+1 prefix of first-pass pyramid regions
     const int32_t *pyr2_pre;  // nprod+1 prefix of second-pass pyramid blocks (1 per product with P > 32)
     const int32_t *morton;    // concatenated Morton orders, product p's at tile_pre[p]
-    int32_t *work;            // tile_pre[nprod] entries: longest-first global tile ids
-    Job *jobs;                // the same list expanded into job records
-    int32_t *work_count;      // device scalar: valid entries in `work` and `jobs`
+    int32_t *work;            // tile_pre[nprod] entries: longest-first global tile ids (of the
+                              // quads' first tiles, for quad products)
+    Job *jobs;                // the same list expanded into job records, four per quad for quad
+                              // products (tile (2i+q/2, 2j+q%2) at 4w+q; cnt -1 past the edge)
+    int32_t *work_count;      // device scalar: valid entries in `work` (tiles or quads)
     int32_t *hist;            // NBUCKET * hist_blocks scratch for the large-table sort
     int hist_blocks;
     int total_cull, total_tiles, total_pyr, total_pyr2;
+    int total_quads;          // sum of ceil(nb/2)^2
     int max_nb;
 };
 
@@ -156,7 +166,8 @@ hipError_t launch_sym_part(const double *src, double *dst, int64_t n, int64_t ld
 
 // Batched stages over a product table.
 hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st);
-// Longest-first job list for leaf tiles of size `leaf` and element size `esz` bytes.
+// Longest-first job list for the leaf products of precision gprec on leaf
+// tiles of side `leaf` (quads of tiles when quad_tiles(gprec, leaf)).
 hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st);
 hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t st);
 hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st);  // pyramid of each product's C

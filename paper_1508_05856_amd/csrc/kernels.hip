@@ -406,13 +406,26 @@ hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st) {
 // Small tables: one workgroup, one bucket per count.  Large tables: NBUCKET
 // coarse buckets (count capped), per-workgroup histograms, a scan, a scatter.
 // ---------------------------------------------------------------------------
+// With quad set, an item is a quad of tiles, named by its first tile (both
+// indices even; the other tiles return -1), and its count is the largest of
+// its tiles' counts.  Going through the tiles in Morton order visits the quads
+// in Morton order of the quad grid.
 __device__ inline int item_count(const ProdDesc *prods, const int32_t *tile_pre, const int32_t *morton, int nprod,
-                                 int g, int &p, int &t) {
+                                 int g, int quad, int &p, int &t) {
     p = find_slot(tile_pre, nprod, g);
     const ProdDesc &d = prods[p];
     if (!prod_running(d)) return -1;
     t = morton[g];
-    return d.cnt[t];
+    if (!quad) return d.cnt[t];
+    const int nb = d.nb, i = t / nb, j = t % nb;
+    if ((i | j) & 1) return -1;
+    int c = d.cnt[t];
+    if (j + 1 < nb) c = max(c, d.cnt[t + 1]);
+    if (i + 1 < nb) {
+        c = max(c, d.cnt[t + nb]);
+        if (j + 1 < nb) c = max(c, d.cnt[t + nb + 1]);
+    }
+    return c;
 }
 
 // Job record of tile t of product p for element size esz (pointers resolved
@@ -447,7 +460,8 @@ constexpr int PLAN_ITEMS = PLAN_SMALL_MAX / 1024;
 __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict__ prods,
                                                      const int32_t *__restrict__ tile_pre,
                                                      const int32_t *__restrict__ morton, int nprod, int max_nb,
-                                                     int32_t *__restrict__ work, int32_t *__restrict__ work_count) {
+                                                     int quad, int32_t *__restrict__ work,
+                                                     int32_t *__restrict__ work_count) {
     extern __shared__ int hist[];  // max_nb + 1 bins
     const int total = tile_pre[nprod];
     for (int c = threadIdx.x; c <= max_nb; c += 1024) hist[c] = 0;
@@ -459,7 +473,7 @@ __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict_
         gid[q] = 0;
         if (g < total) {
             int p, t;
-            cnt[q] = item_count(prods, tile_pre, morton, nprod, g, p, t);
+            cnt[q] = item_count(prods, tile_pre, morton, nprod, g, quad, p, t);
             gid[q] = tile_pre[p] + t;
         }
     }
@@ -488,7 +502,7 @@ __device__ inline int bucket_of(int c) { return c < NBUCKET - 1 ? c : NBUCKET - 
 __global__ __launch_bounds__(256) void k_plan_hist(const ProdDesc *__restrict__ prods,
                                                    const int32_t *__restrict__ tile_pre,
                                                    const int32_t *__restrict__ morton, int nprod, int nblk,
-                                                   int32_t *__restrict__ hist) {
+                                                   int quad, int32_t *__restrict__ hist) {
     __shared__ int h[NBUCKET];
     const int total = tile_pre[nprod];
     const int chunk = (total + nblk - 1) / nblk;
@@ -497,7 +511,7 @@ __global__ __launch_bounds__(256) void k_plan_hist(const ProdDesc *__restrict__ 
     __syncthreads();
     for (int g = lo + threadIdx.x; g < hi; g += 256) {
         int p, t;
-        const int c = item_count(prods, tile_pre, morton, nprod, g, p, t);
+        const int c = item_count(prods, tile_pre, morton, nprod, g, quad, p, t);
         if (c >= 0) atomicAdd(&h[bucket_of(c)], 1);
     }
     __syncthreads();
@@ -540,7 +554,8 @@ __global__ __launch_bounds__(1024) void k_plan_scan(int32_t *__restrict__ hist, 
 __global__ __launch_bounds__(256) void k_plan_scatter(const ProdDesc *__restrict__ prods,
                                                       const int32_t *__restrict__ tile_pre,
                                                       const int32_t *__restrict__ morton, int nprod, int nblk,
-                                                      const int32_t *__restrict__ hist, int32_t *__restrict__ work) {
+                                                      int quad, const int32_t *__restrict__ hist,
+                                                      int32_t *__restrict__ work) {
     __shared__ int cur[NBUCKET];
     const int total = tile_pre[nprod];
     const int chunk = (total + nblk - 1) / nblk;
@@ -549,7 +564,7 @@ __global__ __launch_bounds__(256) void k_plan_scatter(const ProdDesc *__restrict
     __syncthreads();
     for (int g = lo + threadIdx.x; g < hi; g += 256) {
         int p, t;
-        const int c = item_count(prods, tile_pre, morton, nprod, g, p, t);
+        const int c = item_count(prods, tile_pre, morton, nprod, g, quad, p, t);
         if (c >= 0) work[atomicAdd(&cur[bucket_of(c)], 1)] = tile_pre[p] + t;
     }
 }
@@ -559,12 +574,13 @@ __global__ __launch_bounds__(256) void k_plan_scatter(const ProdDesc *__restrict
 // entries q*run .. q*run+run-1 of the window land on workgroups that run on
 // XCD q (workgroup w runs on XCD w mod 8): the window's order in time barely
 // changes, and neighbouring tiles meet in one L2.  The partial last window
-// keeps its order.
+// keeps its order.  With quad set, entry w is a quad and gets the four
+// records 4w .. 4w+3.
 __global__ __launch_bounds__(256) void k_make_jobs(const ProdDesc *__restrict__ prods,
                                                    const int32_t *__restrict__ tile_pre, int nprod,
                                                    const int32_t *__restrict__ work,
                                                    const int32_t *__restrict__ work_count, int b, int esz, int run,
-                                                   Job *__restrict__ jobs) {
+                                                   int quad, Job *__restrict__ jobs) {
     const int idx = blockIdx.x * 256 + threadIdx.x;
     const int count = *work_count;
     if (idx >= count) return;
@@ -580,24 +596,41 @@ __global__ __launch_bounds__(256) void k_make_jobs(const ProdDesc *__restrict__ 
             w = idx - q + (q % run) * 8 + q / run;
         }
     }
-    jobs[w] = make_job(d, t, d.cnt[t], b, esz);
+    if (!quad) {
+        jobs[w] = make_job(d, t, d.cnt[t], b, esz);
+        return;
+    }
+    const int nb = d.nb, i = t / nb, j = t % nb;
+    for (int q = 0; q < 4; ++q) {
+        const int ti = i + (q >> 1), tj = j + (q & 1);
+        Job J;
+        if (ti < nb && tj < nb) {
+            J = make_job(d, ti * nb + tj, d.cnt[ti * nb + tj], b, esz);
+        } else {  // past the edge of an odd nb: no tile, never loaded or written
+            J = make_job(d, t, 0, b, esz);
+            J.cnt = -1;
+        }
+        jobs[4 * w + q] = J;
+    }
 }
 
 hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
     const int esz = gprec == P_F64 ? 8 : 4;
-    const int run = gprec == P_BF16X3 ? BF3_XCD_RUN : 1;
+    const int quad = quad_tiles(gprec, leaf) ? 1 : 0;
+    const int run = gprec == P_BF16X3 ? (quad ? BF3_XCD_RUN / 4 : BF3_XCD_RUN) : 1;
     if (t.hist_blocks == 0) {
         hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), (t.max_nb + 1) * sizeof(int), st, t.prods, t.tile_pre,
-                           t.morton, t.nprod, t.max_nb, t.work, t.work_count);
+                           t.morton, t.nprod, t.max_nb, quad, t.work, t.work_count);
     } else {
         hipLaunchKernelGGL(k_plan_hist, dim3(t.hist_blocks), dim3(256), 0, st, t.prods, t.tile_pre, t.morton,
-                           t.nprod, t.hist_blocks, t.hist);
+                           t.nprod, t.hist_blocks, quad, t.hist);
         hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, t.hist, t.hist_blocks, t.work_count);
         hipLaunchKernelGGL(k_plan_scatter, dim3(t.hist_blocks), dim3(256), 0, st, t.prods, t.tile_pre, t.morton,
-                           t.nprod, t.hist_blocks, t.hist, t.work);
+                           t.nprod, t.hist_blocks, quad, t.hist, t.work);
     }
-    hipLaunchKernelGGL(k_make_jobs, dim3((t.total_tiles + 255) / 256), dim3(256), 0, st, t.prods, t.tile_pre,
-                       t.nprod, t.work, t.work_count, leaf, esz, run, t.jobs);
+    const int items = quad ? t.total_quads : t.total_tiles;
+    hipLaunchKernelGGL(k_make_jobs, dim3((items + 255) / 256), dim3(256), 0, st, t.prods, t.tile_pre, t.nprod,
+                       t.work, t.work_count, leaf, esz, run, quad, t.jobs);
     return hipGetLastError();
 }
 

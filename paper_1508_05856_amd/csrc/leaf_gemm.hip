@@ -1,6 +1,6 @@
 // Leaf products of SpAMM on the gfx950 matrix cores: FP64, FP32 and BF16x3
-// tiles, one workgroup per output tile of a job list, with the fused
-// Newton-Schulz epilogue.  Kept apart from the other kernels so that counter
+// tiles, one workgroup per output tile of a job list (per quad of output
+// tiles for BF16x3 at b = 64), with the fused Newton-Schulz epilogue.  Kept apart from the other kernels so that counter
 // profiles of these kernels can be matched to their source.
 #include <hip/hip_runtime.h>
 
@@ -467,6 +467,263 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16x3 leaf products of 64x64 tiles, one workgroup per quad of output tiles
+// (2i+di, 2j+dj).  Wave w = 2di+dj owns tile (di, dj) whole (4x4 blocks of
+// 16x16).  The workgroup first merges the four retained lists into their
+// union in LDS (increasing k, with a 4-bit mask of the tiles that retain k),
+// then runs the two-stage-ahead pipeline over the union: a stage stages A_ik
+// of each row half and B_kj of each column half that some tile of the mask
+// needs, once for the quad, and each wave whose tile retains k multiplies.
+// Every tile sees its own retained k in increasing order with the MFMA
+// sequence of the one-tile kernel k_leaf_gemm_bf3 (four waves of 32x32
+// quadrants), and its norm and Newton-Schulz partials are summed over the
+// same quadrants in the same order, so a quad's tiles come out bitwise as
+// that kernel computes them at b = 64.
+// A stage holds 32 k.  A planes are rows of 32 bf16 (64 B) whose 16-byte
+// chunks are XOR-swizzled by (row/4) mod 4, so the 16 rows of a fragment read
+// fall in distinct banks; B planes (columns of k, transposed) keep the padded
+// stride of the one-tile kernel, which also keeps the 4-byte k-pair stores
+// conflict-free.
+// ---------------------------------------------------------------------------
+struct Bf3Quad {
+    static constexpr int B = 64;
+    static constexpr int NT = 256;
+    static constexpr int KS = 32;
+    static constexpr int SPT = B / KS;
+    static constexpr int LDA = KS;      // swizzled, unpadded
+    static constexpr int LDB = KS + 8;  // padded
+    static constexpr int A_CH = B * KS / 4 / NT;         // float4 chunks of one A half per thread per stage
+    static constexpr int B_UN = (KS / 2) * (B / 4) / NT;  // (k pair, 4 columns) units of one B half per thread
+};
+static_assert(Bf3Quad::A_CH == 2 && Bf3Quad::B_UN == 1, "stage split assumed below");
+
+__device__ inline int swz_a(int row, int k) {  // bf16 offset of (row, k) in an A plane
+    return row * Bf3Quad::LDA + ((((k >> 3) ^ (row >> 2)) & 3) << 3) + (k & 7);
+}
+
+__global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restrict__ jobs,
+                                                           const int32_t *__restrict__ work_count) {
+    using C = Bf3Quad;
+    constexpr int B = C::B;
+    // [buffer][row half di / column half dj][plane hi/lo][...]
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][2][2][B * C::LDA];
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[2][2][2][B * C::LDB];
+    __shared__ unsigned umask[QUAD_NB_MAX / 4];  // byte k%4 of word k/4: tiles retaining k
+    __shared__ unsigned ulist[QUAD_NB_MAX];      // k | mask << 16, increasing k
+    __shared__ int wtot[4];
+
+    const int nwork = *work_count;
+    if ((int)blockIdx.x >= nwork) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const Job J = jobs[4 * blockIdx.x + w];  // this wave's tile
+    const int nb = jobs[4 * blockIdx.x].nb;
+    const gptr<const float> Arow[2] = {to_global((const float *)jobs[4 * blockIdx.x].a_row),
+                                       to_global((const float *)jobs[4 * blockIdx.x + 2].a_row)};
+    const gptr<const float> Bcol[2] = {to_global((const float *)jobs[4 * blockIdx.x].b_col),
+                                       to_global((const float *)jobs[4 * blockIdx.x + 1].b_col)};
+    constexpr int64_t TS = (int64_t)B * B;
+
+    // union of the four retained lists
+    const int nwords = (nb + 3) / 4;
+    for (int x = tid; x < nwords; x += C::NT) umask[x] = 0u;
+    __syncthreads();
+    if (J.cnt > 0) {
+        const gptr<const int32_t> list = to_global(J.list);
+        for (int e = lane; e < J.cnt; e += 64) {
+            const int k = list[e];
+            atomicOr(&umask[k >> 2], 1u << (8 * (k & 3) + w));
+        }
+    }
+    __syncthreads();
+    // one word (4 consecutive k) per thread: nb <= QUAD_NB_MAX = 4 * NT
+    const unsigned word = tid < nwords ? umask[tid] : 0u;
+    const int mine = (int)((word & 0xffu) != 0) + (int)((word & 0xff00u) != 0) + (int)((word & 0xff0000u) != 0) +
+                     (int)((word & 0xff000000u) != 0);
+    int incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int pos = incl - mine;
+    for (int x = 0; x < w; ++x) pos += wtot[x];
+    const int U = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const unsigned m = (word >> (8 * q)) & 0xfu;
+        if (m) ulist[pos++] = (unsigned)(4 * tid + q) | (m << 16);
+    }
+    __syncthreads();
+
+    const int S = U * C::SPT;
+    const int di = w >> 1, dj = w & 1;
+
+    v4f acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0.0f;
+
+    // operands a half needs: A row half h for tiles 2h, 2h+1; B column half h for tiles h, h+2
+    auto needA = [](unsigned m, int h) { return (m & (h ? 0xcu : 0x3u)) != 0u; };
+    auto needB = [](unsigned m, int h) { return (m & (h ? 0xau : 0x5u)) != 0u; };
+    // registers of one stage: [0..3] A halves 0, 1 (A_CH chunks each), [4..7] B halves 0, 1 (rows 2kp, 2kp+1)
+    auto gload = [&](int s, v4f *r) {
+        const unsigned e = ulist[s / C::SPT];
+        const int k = (int)(e & 0xffffu);
+        const unsigned m = e >> 16;
+        const int ks = s % C::SPT;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (needA(m, h)) {
+                const gptr<const float> a = Arow[h] + (int64_t)k * TS + ks * C::KS;
+#pragma unroll
+                for (int c = 0; c < C::A_CH; ++c) {
+                    const int el = (tid + c * C::NT) * 4;
+                    r[2 * h + c] = *(gptr<const v4f>)(a + (el / C::KS) * B + el % C::KS);
+                }
+            }
+            if (needB(m, h)) {
+                const gptr<const float> b = Bcol[h] + (int64_t)k * nb * TS + (int64_t)ks * C::KS * B;
+                const int kp = tid % (C::KS / 2), cg = tid / (C::KS / 2);
+                r[4 + 2 * h] = *(gptr<const v4f>)(b + (2 * kp) * B + 4 * cg);
+                r[5 + 2 * h] = *(gptr<const v4f>)(b + (2 * kp + 1) * B + 4 * cg);
+            }
+        }
+    };
+    auto sstore = [&](int buf, int s, const v4f *r) {
+        const unsigned m = ulist[s / C::SPT] >> 16;
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (needA(m, h)) {
+#pragma unroll
+                for (int c = 0; c < C::A_CH; ++c) {
+                    const int el = (tid + c * C::NT) * 4;
+                    const int row = el / C::KS, k = el % C::KS;
+                    unsigned h0, l0, h1, l1;
+                    split2(r[2 * h + c][0], r[2 * h + c][1], h0, l0);
+                    split2(r[2 * h + c][2], r[2 * h + c][3], h1, l1);
+                    *(u2 *)&As[buf][h][0][swz_a(row, k)] = u2{h0, h1};
+                    *(u2 *)&As[buf][h][1][swz_a(row, k)] = u2{l0, l1};
+                }
+            }
+            if (needB(m, h)) {
+                const int kp = tid % (C::KS / 2), cg = tid / (C::KS / 2);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    unsigned hi, lo;
+                    split2(r[4 + 2 * h][q], r[5 + 2 * h][q], hi, lo);  // (k, k+1) of column 4cg+q
+                    const int col = 4 * cg + q;
+                    *(unsigned *)&Bt[buf][h][0][col * C::LDB + 2 * kp] = hi;
+                    *(unsigned *)&Bt[buf][h][1][col * C::LDB + 2 * kp] = lo;
+                }
+            }
+        }
+    };
+    auto compute = [&](int buf, int s) {
+        const unsigned m = ulist[s / C::SPT] >> 16;
+        if (!((m >> w) & 1u)) return;
+        // operand layout of the 16x16x32 bf16 MFMA: lane l supplies row (A) or
+        // column (B) l%16 at k = 8(l/16) .. 8(l/16)+7
+        const int ko = 8 * (lane >> 4);
+        bf16x8 ah[4], al[4];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) {
+            const int row = bi * 16 + (lane & 15);
+            ah[bi] = *(const bf16x8 *)&As[buf][di][0][swz_a(row, ko)];
+            al[bi] = *(const bf16x8 *)&As[buf][di][1][swz_a(row, ko)];
+        }
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int col = bj * 16 + (lane & 15);
+            const bf16x8 bh = *(const bf16x8 *)&Bt[buf][dj][0][col * C::LDB + ko];
+            const bf16x8 bl = *(const bf16x8 *)&Bt[buf][dj][1][col * C::LDB + ko];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) {
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bh, acc[bi][bj], 0, 0, 0);
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bl, acc[bi][bj], 0, 0, 0);
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bh, acc[bi][bj], 0, 0, 0);
+            }
+        }
+    };
+
+    v4f r0[8], r1[8];
+    if (S > 0) {
+        gload(0, r0);
+        if (S > 1) gload(1, r1);
+        sstore(0, 0, r0);
+        if (S > 2) gload(2, r0);
+    }
+    __syncthreads();
+    for (int s = 0; s < S; s += 2) {
+        if (s + 1 < S) sstore(1, s + 1, r1);
+        if (s + 3 < S) gload(s + 3, r1);
+        compute(0, s);
+        __syncthreads();
+        if (s + 1 >= S) break;
+        if (s + 2 < S) sstore(0, s + 2, r0);
+        if (s + 4 < S) gload(s + 4, r0);
+        compute(1, s + 1);
+        __syncthreads();
+    }
+
+    // epilogue, per wave: its tile (FP32), FP64 norm and Newton-Schulz
+    // partials, each summed per 32x32 quadrant then over the quadrants in order
+    if (J.cnt < 0) return;  // past the edge
+    const bool nsx = J.part != nullptr;
+    const gptr<float> Ct = to_global((float *)J.c);
+    double qa = 0.0, r2a = 0.0, tra = 0.0;
+#pragma unroll
+    for (int quad = 0; quad < 4; ++quad) {
+        const int wr = quad >> 1, wc = quad & 1;
+        double qs = 0.0, r2 = 0.0, tr = 0.0;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wr * 32 + bi * 16 + 4 * (lane >> 4) + r;
+                    const int col = wc * 32 + bj * 16 + (lane & 15);
+                    const double x = (double)acc[2 * wr + bi][2 * wc + bj][r];
+                    float out;
+                    if (nsx) {
+                        const int64_t gi = (int64_t)J.i * B + row, gj = (int64_t)J.j * B + col;
+                        const bool diag = (gi == gj) && (gi < J.n);
+                        const bool logical = (gi < J.n) && (gj < J.n);
+                        const double h = (diag ? 1.5 : 0.0) - 0.5 * x;
+                        const double ex = (diag ? 1.0 : 0.0) - x;
+                        if (logical) r2 += ex * ex;
+                        if (diag) tr += x;
+                        out = J.fused_map ? (float)h : (float)x;
+                    } else {
+                        out = (float)x;
+                    }
+                    Ct[row * B + col] = out;
+                    const double dv = (double)out;
+                    qs += dv * dv;
+                }
+        qa += wave_sum(qs);
+        if (nsx) {
+            r2a += wave_sum(r2);
+            tra += wave_sum(tr);
+        }
+    }
+    if (lane == 0) {
+        *to_global(J.qc) = qa;
+        if (nsx) {
+            to_global(J.part)[0] = r2a;
+            to_global(J.part)[1] = tra;
+        }
+    }
+}
+
 template <typename T, int B>
 static void gemm_launch(const ProdTable &t, hipStream_t st) {
     hipLaunchKernelGGL((k_leaf_gemm<T, B>), dim3(t.total_tiles), dim3(TileCfg<T, B>::NT), 0, st, t.jobs,
@@ -487,8 +744,9 @@ hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t s
     if (prec == P_F64) {
         gemm_dispatch_b<double>(leaf, t, st);
     } else if (prec == P_BF16X3) {
-        if (leaf == 64)
-            hipLaunchKernelGGL(k_leaf_gemm_bf3<64>, dim3(t.total_tiles), dim3(256), 0, st, t.jobs, t.work_count);
+        if (quad_tiles(prec, leaf))  // leaf 64
+            hipLaunchKernelGGL(k_leaf_gemm_bf3_quad, dim3(t.total_quads), dim3(Bf3Quad::NT), 0, st, t.jobs,
+                               t.work_count);
         else if (leaf == 32)
             hipLaunchKernelGGL(k_leaf_gemm_bf3<32>, dim3(t.total_tiles), dim3(64), 0, st, t.jobs, t.work_count);
         else
