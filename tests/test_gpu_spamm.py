@@ -153,7 +153,8 @@ def test_multiply_f32_error_vs_oracle(ctx):
     assert err < 1e-6
 
 
-@pytest.mark.parametrize("n,leaf", [(500, 32), (640, 64), (64, 64), (1600, 32), (1630, 64)])
+@pytest.mark.parametrize("n,leaf", [(500, 32), (640, 64), (64, 64), (100, 64), (1600, 32), (1600, 64),
+                                    (1630, 64)])
 def test_multiply_bf16x3_error_vs_oracle(ctx, n, leaf):
     """BF16x3 leaves: operands are stored in FP32, so the cull sees the FP32
     values and R must equal the oracle's R on the FP32-rounded inputs.  Each
@@ -162,9 +163,11 @@ def test_multiply_bf16x3_error_vs_oracle(ctx, n, leaf):
     plus FP32 accumulation; the bound used is 2^-13 sum_R |A_ik||B_kj|
     elementwise (the oracle's SpAMM of |A|, |B| has the same norms, hence the
     same R).  A single bf16 product would be ~2^-9 off, so the Frobenius error
-    must also be far below that.  The two larger cases have 2500 and 676
-    tiles, so the BF16x3 job order (windows of 512 jobs spread over the XCDs)
-    has full windows and a ragged last one."""
+    must also be far below that.  Leaf 64 runs one workgroup per quad of
+    tiles: nb = 1 and 25 leave quads with missing tiles at the edge, nb = 2 is
+    a single full quad.  The cases n = 1600 at leaf 32 (2500 tiles) and
+    n = 1630 at leaf 64 (169 quads) fill the BF16x3 job order's windows of 512
+    tiles or 128 quads spread over the XCDs, with a ragged last window."""
     tau = 1e-6
     a = decaying(n, seed=17, rate=0.05).astype(np.float32).astype(np.float64)
     b = decaying(n, seed=18, rate=0.05).astype(np.float32).astype(np.float64)
