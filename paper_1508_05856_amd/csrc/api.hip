@@ -537,6 +537,17 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
     return SPAMM_OK;
 }
 
+// Cull and job list of one table: one launch for small tables.
+int enqueue_front(spamm_ctx *ctx, const ProdTable &t, int leaf, int gprec, hipStream_t st) {
+    if (front_small(t, leaf, gprec)) {
+        TIMED(K_CULL, launch_front_small(t, leaf, gprec, st));
+    } else {
+        TIMED(K_CULL, launch_cull_tab(t, st));
+        HIPCHK(launch_plan_tab(t, leaf, gprec, st));
+    }
+    return SPAMM_OK;
+}
+
 // One Newton-Schulz iteration of every running solve of a plan.
 int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
     const int kp = kernel_prec(p->prec);
@@ -545,31 +556,26 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
         // map); z_{k+1} = z_k (x)_tau h_k
         HIPCHK(launch_transpose_tab(kp, p->tt, p->leaf, st));
         TIMED(K_PYR, launch_pyramid_tab(p->tt, st));
-        TIMED(K_CULL, launch_cull_tab(p->ty, st));
-        HIPCHK(launch_plan_tab(p->ty, p->leaf, gemm_prec(p->prec), st));
+        TRY(enqueue_front(ctx, p->ty, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->ty, st));
         TIMED(K_PYR, launch_pyramid_tab(p->ty, st));
-        TIMED(K_CULL, launch_cull_tab(p->tx, st));
-        HIPCHK(launch_plan_tab(p->tx, p->leaf, gemm_prec(p->prec), st));
+        TRY(enqueue_front(ctx, p->tx, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
         HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
         if (p->damped) HIPCHK(launch_ns_map(kp, p->tx, p->leaf, st));
         TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
-        TIMED(K_CULL, launch_cull_tab(p->tz, st));
-        HIPCHK(launch_plan_tab(p->tz, p->leaf, gemm_prec(p->prec), st));
+        TRY(enqueue_front(ctx, p->tz, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tz, st));
         TIMED(K_PYR, launch_pyramid_tab(p->tz, st));
         HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
         return SPAMM_OK;
     }
-    TIMED(K_CULL, launch_cull_tab(p->tx, st));
-    HIPCHK(launch_plan_tab(p->tx, p->leaf, gemm_prec(p->prec), st));
+    TRY(enqueue_front(ctx, p->tx, p->leaf, gemm_prec(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
     HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
     if (p->damped) HIPCHK(launch_ns_map(kp, p->tx, p->leaf, st));
     TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
-    TIMED(K_CULL, launch_cull_tab(p->tyz, st));
-    HIPCHK(launch_plan_tab(p->tyz, p->leaf, gemm_prec(p->prec), st));
+    TRY(enqueue_front(ctx, p->tyz, p->leaf, gemm_prec(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tyz, st));
     TIMED(K_PYR, launch_pyramid_tab(p->tyz, st));
     HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
@@ -834,8 +840,7 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     ProdTable t = layout_table(c, prods, &image);
     image.resize(c.off);
     HIPCHK(hipMemcpyAsync(ctx->buf[S_TAB], image.data(), image.size(), hipMemcpyHostToDevice, st));
-    TIMED(K_CULL, launch_cull_tab(t, st));
-    HIPCHK(launch_plan_tab(t, leaf, gemm_prec(prec), st));
+    TRY(enqueue_front(ctx, t, leaf, gemm_prec(prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(prec), leaf, t, st));
     HIPCHK(launch_egress(kp, g, ctx->buf[S_T2], C, ld, 1.0, 0, st));
     int status = SPAMM_OK;

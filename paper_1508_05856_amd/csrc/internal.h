@@ -170,6 +170,13 @@ hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st);
 // tiles of side `leaf` (quads of tiles when quad_tiles(gprec, leaf)).
 hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st);
 hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t st);
+// Tables of at most FRONT_MAX tiles and FRONT_PRODS products (and not quad
+// products): cull and job list in one single-workgroup launch, in place of
+// launch_cull_tab followed by launch_plan_tab.
+constexpr int FRONT_MAX = 1024;
+constexpr int FRONT_PRODS = 256;
+bool front_small(const ProdTable &t, int leaf, int gprec);
+hipError_t launch_front_small(const ProdTable &t, int leaf, int gprec, hipStream_t st);
 hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st);  // pyramid of each product's C
 // Per solve: r_k, t_k, |R| records and the stop decision.
 hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, hipStream_t st);

@@ -362,22 +362,18 @@ hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st) {
 // A's leaf norms and a column of B's (from the transposed copy) are read
 // coalesced.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cull_tab(const ProdDesc *__restrict__ prods,
-                                                  const int32_t *__restrict__ pre, int nprod) {
-    const int p = find_slot(pre, nprod, blockIdx.x);
-    const ProdDesc &d = prods[p];
-    if (!prod_running(d)) return;
+// Cull of tile t of a running product by one wave (lane = lane index);
+// returns the count, and the first two kept k in k0, k1 (-1 when absent).
+__device__ inline int cull_tile(const ProdDesc &d, int t, int lane, int &k0, int &k1) {
     const int par = prod_parity(d);
     const int nb = d.nb;
-    const int t = (blockIdx.x - pre[p]) * 4 + (threadIdx.x >> 6);
-    if (t >= nb * nb) return;
-    const int lane = threadIdx.x & 63;
     const int i = t / nb, j = t % nb;
     const double thr = d.tau * (sqrt(*d.rootA[par]) * sqrt(*d.rootB[par]));
     const double *na = d.nrmA[par] + (int64_t)i * nb;
     const double *nbt = d.nrmB[par] + (int64_t)nb * nb + (int64_t)j * nb;  // ||B_kj|| at nbt[k]
     int32_t *out = d.kidx + (int64_t)t * nb;
     int base = 0;
+    k0 = k1 = -1;
     for (int kb = 0; kb < nb; kb += 64) {
         const int k = kb + lane;
         bool keep = false;
@@ -387,9 +383,32 @@ __global__ __launch_bounds__(256) void k_cull_tab(const ProdDesc *__restrict__ p
         }
         const unsigned long long mask = __ballot(keep);
         if (keep) out[base + __popcll(mask & ((1ull << lane) - 1ull))] = k;
+        if (base < 2 && mask) {  // wave-uniform
+            unsigned long long m = mask;
+            int f = base;
+            while (f < 2 && m) {
+                const int kk = kb + __ffsll((long long)m) - 1;
+                if (f == 0) k0 = kk; else k1 = kk;
+                m &= m - 1ull;
+                ++f;
+            }
+        }
         base += __popcll(mask);
     }
-    if (lane == 0) d.cnt[t] = base;
+    return base;
+}
+
+__global__ __launch_bounds__(256) void k_cull_tab(const ProdDesc *__restrict__ prods,
+                                                  const int32_t *__restrict__ pre, int nprod) {
+    const int p = find_slot(pre, nprod, blockIdx.x);
+    const ProdDesc &d = prods[p];
+    if (!prod_running(d)) return;
+    const int t = (blockIdx.x - pre[p]) * 4 + (threadIdx.x >> 6);
+    if (t >= d.nb * d.nb) return;
+    const int lane = threadIdx.x & 63;
+    int k0, k1;
+    const int cnt = cull_tile(d, t, lane, k0, k1);
+    if (lane == 0) d.cnt[t] = cnt;
 }
 
 hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st) {
@@ -430,8 +449,9 @@ __device__ inline int item_count(const ProdDesc *prods, const int32_t *tile_pre,
 
 // Job record of tile t of product p for element size esz (pointers resolved
 // for the product's current parity).
-__device__ inline Job make_job(const ProdDesc &d, int t, int cnt, int b, int esz) {
-    const int par = prod_parity(d);
+// Job record of tile t of product d at parity par, with the tile's first two
+// retained k given.
+__device__ inline Job make_job_kp(const ProdDesc &d, int par, int t, int cnt, int b, int esz, int k0, int k1) {
     const int nb = d.nb, i = t / nb, j = t % nb;
     const int64_t ts = (int64_t)b * b * esz;
     Job J;
@@ -447,9 +467,28 @@ __device__ inline Job make_job(const ProdDesc &d, int t, int cnt, int b, int esz
     J.i = i;
     J.j = j;
     J.fused_map = d.fused_map;
-    J.k0 = cnt > 0 ? J.list[0] : 0;
-    J.k1 = cnt > 1 ? J.list[1] : 0;
+    J.k0 = cnt > 0 ? k0 : 0;
+    J.k1 = cnt > 1 ? k1 : 0;
     return J;
+}
+
+// The same at the product's current parity, with the first two retained k
+// read from the tile's list.
+__device__ inline Job make_job(const ProdDesc &d, int t, int cnt, int b, int esz) {
+    const int32_t *list = d.kidx + (int64_t)t * d.nb;
+    return make_job_kp(d, prod_parity(d), t, cnt, b, esz, cnt > 0 ? list[0] : 0, cnt > 1 ? list[1] : 0);
+}
+
+// Slot of entry idx of a longest-first list of `count` entries after the XCD
+// runs: each window of 8*run entries is transposed so that entries
+// q*run .. q*run+run-1 of the window land on workgroups that run on XCD q
+// (workgroup w runs on XCD w mod 8); the partial last window keeps its order.
+__device__ inline int xcd_slot(int idx, int count, int run) {
+    if (run <= 1) return idx;
+    const int W = 8 * run;
+    if (idx >= count / W * W) return idx;
+    const int q = idx % W;
+    return idx - q + (q % run) * 8 + q / run;
 }
 
 // Small tables (<= PLAN_ITEMS * 1024 tiles, the tables without hist_blocks):
@@ -569,13 +608,10 @@ __global__ __launch_bounds__(256) void k_plan_scatter(const ProdDesc *__restrict
     }
 }
 
-// Expands the sorted tile ids into job records, one thread per entry.  With
-// run > 1, each window of 8*run consecutive entries is transposed so that
-// entries q*run .. q*run+run-1 of the window land on workgroups that run on
-// XCD q (workgroup w runs on XCD w mod 8): the window's order in time barely
-// changes, and neighbouring tiles meet in one L2.  The partial last window
-// keeps its order.  With quad set, entry w is a quad and gets the four
-// records 4w .. 4w+3.
+// Expands the sorted tile ids into job records, one thread per entry, at the
+// slots of the XCD runs (xcd_slot): the window's order in time barely
+// changes, and neighbouring tiles meet in one L2.  With quad set, entry w is
+// a quad and gets the four records 4w .. 4w+3.
 __global__ __launch_bounds__(256) void k_make_jobs(const ProdDesc *__restrict__ prods,
                                                    const int32_t *__restrict__ tile_pre, int nprod,
                                                    const int32_t *__restrict__ work,
@@ -588,14 +624,7 @@ __global__ __launch_bounds__(256) void k_make_jobs(const ProdDesc *__restrict__ 
     const int p = find_slot(tile_pre, nprod, gid);
     const int t = gid - tile_pre[p];
     const ProdDesc &d = prods[p];
-    int w = idx;
-    if (run > 1) {
-        const int W = 8 * run;
-        if (idx < count / W * W) {
-            const int q = idx % W;
-            w = idx - q + (q % run) * 8 + q / run;
-        }
-    }
+    const int w = xcd_slot(idx, count, run);
     if (!quad) {
         jobs[w] = make_job(d, t, d.cnt[t], b, esz);
         return;
@@ -612,6 +641,140 @@ __global__ __launch_bounds__(256) void k_make_jobs(const ProdDesc *__restrict__ 
         }
         jobs[4 * w + q] = J;
     }
+}
+
+// Tables of at most FRONT_MAX tiles and FRONT_PRODS products (launch-bound
+// solves): cull, longest-first order and job records in one workgroup, one
+// launch instead of three.  Such tables have nb <= 32, so their leaf norms
+// fit in LDS: one round of parallel loads brings the table's prefix, every
+// product's threshold, state and pointers, and both operands' leaf norms into
+// LDS; the cull then reads LDS only, with 64/L tiles per wave (L lanes per
+// tile, L the power of two >= the largest nb, lane = k).  The counts and
+// first two retained k stay in LDS for the order and the job records.  The
+// lists and counts written, and the order, are those of k_cull_tab and
+// k_plan_small.
+__global__ __launch_bounds__(1024) void k_front_small(const ProdDesc *__restrict__ prods,
+                                                      const int32_t *__restrict__ tile_pre,
+                                                      const int32_t *__restrict__ morton, int nprod, int max_nb,
+                                                      int b, int esz, int run, Job *__restrict__ jobs,
+                                                      int32_t *__restrict__ work_count) {
+    __shared__ int s_pre[FRONT_PRODS + 1];
+    __shared__ int s_par[FRONT_PRODS];  // parity, or -1 when the product is not running
+    __shared__ int s_nbk[FRONT_PRODS];
+    __shared__ double s_thr[FRONT_PRODS];
+    __shared__ int32_t *s_kidx[FRONT_PRODS];
+    __shared__ int32_t *s_cntp[FRONT_PRODS];
+    __shared__ const double *s_nra[FRONT_PRODS], *s_nrb[FRONT_PRODS];  // leaf norms at the current parity
+    __shared__ double s_na[FRONT_MAX], s_nb[FRONT_MAX];  // A's leaf norms, B's transposed, product q's at s_pre[q]
+    __shared__ int s_cnt[FRONT_MAX], s_k0[FRONT_MAX], s_k1[FRONT_MAX];
+    __shared__ int s_total;
+    extern __shared__ int hist[];  // max_nb + 1 bins
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ntile = tile_pre[nprod];
+    const int mort = tid < ntile ? morton[tid] : 0;  // read now, used by the ordering
+    for (int x = tid; x <= nprod; x += 1024) s_pre[x] = tile_pre[x];
+    for (int c = tid; c <= max_nb; c += 1024) hist[c] = 0;
+    for (int q = tid; q < nprod; q += 1024) {
+        const ProdDesc &d = prods[q];
+        const int par = prod_running(d) ? prod_parity(d) : -1;
+        s_par[q] = par;
+        s_nbk[q] = d.nb;
+        s_kidx[q] = d.kidx;
+        s_cntp[q] = d.cnt;
+        if (par >= 0) {
+            s_thr[q] = d.tau * (sqrt(*d.rootA[par]) * sqrt(*d.rootB[par]));
+            s_nra[q] = d.nrmA[par];
+            s_nrb[q] = d.nrmB[par] + (int64_t)d.nb * d.nb;
+        }
+    }
+    __syncthreads();
+    const int total = s_pre[nprod];
+    for (int g = tid; g < total; g += 1024) {
+        const int q = find_slot(s_pre, nprod, g);
+        if (s_par[q] < 0) continue;
+        const int x = g - s_pre[q];
+        s_na[g] = s_nra[q][x];
+        s_nb[g] = s_nrb[q][x];
+    }
+    __syncthreads();
+    // cull: lane l tests k = l % L of tile l / L of the wave's group
+    int L = 1;
+    while (L < max_nb) L <<= 1;
+    const int per = 64 / L, sub = lane / L, k = lane % L;
+    const unsigned long long lmask = L == 64 ? ~0ull : ((1ull << L) - 1ull);
+    for (int g0 = per * wv; g0 < total; g0 += 16 * per) {
+        const int g = g0 + sub;
+        int q = 0, nb = 1, t = 0;
+        bool keep = false, live = false;
+        if (g < total) {
+            q = find_slot(s_pre, nprod, g);
+            live = s_par[q] >= 0;
+            if (live) {
+                nb = s_nbk[q];
+                t = g - s_pre[q];
+                const int i = t / nb, j = t % nb;
+                if (k < nb) {
+                    const double prod = s_na[s_pre[q] + i * nb + k] * s_nb[s_pre[q] + j * nb + k];
+                    keep = !(prod < s_thr[q]);
+                }
+            }
+        }
+        const unsigned long long mine = (__ballot(keep) >> (L * sub)) & lmask;
+        if (keep) s_kidx[q][(int64_t)t * nb + __popcll(mine & ((1ull << k) - 1ull))] = k;
+        if (g < total && k == 0) {
+            int cnt = -1, k0 = -1, k1 = -1;
+            if (live) {
+                cnt = __popcll(mine);
+                if (mine) {
+                    k0 = __ffsll((long long)mine) - 1;
+                    const unsigned long long rest = mine & (mine - 1ull);
+                    if (rest) k1 = __ffsll((long long)rest) - 1;
+                }
+                s_cntp[q][t] = cnt;
+            }
+            s_cnt[g] = cnt;
+            s_k0[g] = k0;
+            s_k1[g] = k1;
+        }
+    }
+    __syncthreads();
+    // longest-first order over the items in Morton order, one item per thread
+    int c = -1, gt = 0, q = 0, t = 0;
+    if (tid < total) {
+        q = find_slot(s_pre, nprod, tid);
+        t = mort;
+        gt = s_pre[q] + t;
+        c = s_cnt[gt];
+        if (c >= 0) atomicAdd(&hist[c], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int r = 0;
+        for (int x = max_nb; x >= 0; --x) {
+            const int h = hist[x];
+            hist[x] = r;
+            r += h;
+        }
+        *work_count = r;
+        s_total = r;
+    }
+    __syncthreads();
+    if (c >= 0) {
+        const int idx = atomicAdd(&hist[c], 1);
+        jobs[xcd_slot(idx, s_total, run)] = make_job_kp(prods[q], s_par[q], t, c, b, esz, s_k0[gt], s_k1[gt]);
+    }
+}
+
+bool front_small(const ProdTable &t, int leaf, int gprec) {
+    return t.total_tiles <= FRONT_MAX && t.nprod <= FRONT_PRODS && !quad_tiles(gprec, leaf);
+}
+
+hipError_t launch_front_small(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
+    const int esz = gprec == P_F64 ? 8 : 4;
+    const int run = gprec == P_BF16X3 ? BF3_XCD_RUN : 1;
+    hipLaunchKernelGGL(k_front_small, dim3(1), dim3(1024), (t.max_nb + 1) * sizeof(int), st, t.prods, t.tile_pre,
+                       t.morton, t.nprod, t.max_nb, leaf, esz, run, t.jobs, t.work_count);
+    return hipGetLastError();
 }
 
 hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
