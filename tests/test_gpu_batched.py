@@ -94,6 +94,32 @@ def test_batched_uneven_solves_match_oracle_and_solo(ctx):
         assert rel(Y, ores["Y"]) <= 1e-12 and rel(Z, ores["Z"]) <= 1e-12
 
 
+def test_batched_large_tables_match_solo(ctx):
+    """Tables of more than 1024 tiles take the parallel cull, the multi-block
+    longest-first sort and the job expansion (smaller ones take the one-launch
+    front): four solves at leaf 32, three with more than 1024 tiles each (and
+    one small one in the same tables), at different tau so that they stop at
+    different steps, must match their solo runs bitwise."""
+    specs = [("kms", 1100, 0.8, 0, 1e-8), ("gauss", 1200, 1.0, 1, 1e-6), ("kms", 1056, 0.6, 2, 1e-4),
+             ("kms", 200, 0.7, 3, 1e-6)]
+    mats = [make(k, n, p, sd) for (k, n, p, sd, _) in specs]
+    solos = [solo(ctx, s, 32, tau) for s, (_, _, _, _, tau) in zip(mats, specs)]
+    solves = [ctx.solve_begin(dev(s), tau, 1e-10, 30, leaf=32, stagnation_stop=True)
+              for s, (_, _, _, _, tau) in zip(mats, specs)]
+    steps = 0
+    while ctx.solve_step(solves, 3) > 0:
+        steps += 1
+        assert steps < 40
+    its = set()
+    for sv, (Ys, Zs, infos) in zip(solves, solos):
+        Y, Z, info = sv.finish()
+        assert info["status"] == infos["status"] and info["iterations"] == infos["iterations"]
+        np.testing.assert_array_equal(host(Y), Ys)
+        np.testing.assert_array_equal(host(Z), Zs)
+        its.add(info["iterations"])
+    assert len(its) > 1  # the solves left the shared launches at different steps
+
+
 def test_continuous_batching_join_and_leave(ctx):
     mats = [make(k, n, p, sd) for (k, n, p, sd, _, _) in CASES]
     solos = [solo(ctx, s, leaf, tau) for s, (_, _, _, _, leaf, tau) in zip(mats, CASES)]
