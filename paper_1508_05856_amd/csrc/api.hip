@@ -235,7 +235,8 @@ TableSizes table_sizes(const std::vector<ProdDesc> &prods) {
         z.total_pyr2 += d.P > 32 ? 1 : 0;
         z.max_nb = std::max(z.max_nb, d.nb);
     }
-    z.hist_blocks = z.total_tiles <= PLAN_SMALL_MAX ? 0 : std::min(1024, (z.total_tiles + 4095) / 4096);
+    const int per_block = 256 * PLAN_HIST_ITEMS;
+    z.hist_blocks = z.total_tiles <= PLAN_SMALL_MAX ? 0 : std::min(1024, (z.total_tiles + per_block - 1) / per_block);
     return z;
 }
 

@@ -88,6 +88,7 @@ struct ProdDesc {
 
 constexpr int NBUCKET = 64;          // longest-first buckets of the large-table work-list sort
 constexpr int PLAN_SMALL_MAX = 16384;  // tables up to this many tiles are sorted by one workgroup
+constexpr int PLAN_HIST_ITEMS = 4;     // items per thread and pass of the large-table sort
 // BF16x3 leaf products: consecutive jobs of the longest-first order run in
 // groups of this many tiles on one XCD (workgroup w runs on XCD w mod 8), so
 // neighbouring tiles share that XCD's L2.

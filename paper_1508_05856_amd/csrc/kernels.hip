@@ -538,20 +538,37 @@ __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict_
 
 __device__ inline int bucket_of(int c) { return c < NBUCKET - 1 ? c : NBUCKET - 1; }
 
+// The large-table passes give each thread PLAN_HIST_ITEMS items whose count
+// chains (Morton order, product state, count) are issued together, and read
+// the table's prefix from LDS when it fits.
+constexpr int PRE_LDS = 1024;
+
 __global__ __launch_bounds__(256) void k_plan_hist(const ProdDesc *__restrict__ prods,
                                                    const int32_t *__restrict__ tile_pre,
                                                    const int32_t *__restrict__ morton, int nprod, int nblk,
                                                    int quad, int32_t *__restrict__ hist) {
     __shared__ int h[NBUCKET];
-    const int total = tile_pre[nprod];
-    const int chunk = (total + nblk - 1) / nblk;
-    const int lo = blockIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
+    __shared__ int s_pre[PRE_LDS + 1];
+    const bool lds = nprod <= PRE_LDS;
+    if (lds)
+        for (int x = threadIdx.x; x <= nprod; x += 256) s_pre[x] = tile_pre[x];
     for (int b = threadIdx.x; b < NBUCKET; b += 256) h[b] = 0;
     __syncthreads();
-    for (int g = lo + threadIdx.x; g < hi; g += 256) {
-        int p, t;
-        const int c = item_count(prods, tile_pre, morton, nprod, g, quad, p, t);
-        if (c >= 0) atomicAdd(&h[bucket_of(c)], 1);
+    const int32_t *pre = lds ? s_pre : tile_pre;
+    const int total = pre[nprod];
+    const int chunk = (total + nblk - 1) / nblk;
+    const int lo = blockIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
+    for (int base = lo; base < hi; base += 256 * PLAN_HIST_ITEMS) {
+        int c[PLAN_HIST_ITEMS];
+#pragma unroll
+        for (int q = 0; q < PLAN_HIST_ITEMS; ++q) {
+            const int g = base + threadIdx.x + q * 256;
+            int p, t;
+            c[q] = g < hi ? item_count(prods, pre, morton, nprod, g, quad, p, t) : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < PLAN_HIST_ITEMS; ++q)
+            if (c[q] >= 0) atomicAdd(&h[bucket_of(c[q])], 1);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < NBUCKET; b += 256) hist[b * nblk + blockIdx.x] = h[b];
@@ -560,7 +577,7 @@ __global__ __launch_bounds__(256) void k_plan_hist(const ProdDesc *__restrict__ 
 // Exclusive scan of hist in the order (bucket descending, block ascending).
 __global__ __launch_bounds__(1024) void k_plan_scan(int32_t *__restrict__ hist, int nblk,
                                                     int32_t *__restrict__ work_count) {
-    __shared__ int part[1024];
+    __shared__ int wsum[16];
     const int m = NBUCKET * nblk;
     const int per = (m + 1023) / 1024;
     const int lo = threadIdx.x * per, hi = lo + per < m ? lo + per : m;
@@ -570,19 +587,20 @@ __global__ __launch_bounds__(1024) void k_plan_scan(int32_t *__restrict__ hist, 
     };
     int s = 0;
     for (int L = lo; L < hi; ++L) s += at(L);
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int x = 0; x < 1024; ++x) {
-            const int v = part[x];
-            part[x] = run;
-            run += v;
-        }
-        *work_count = run;
+    // exclusive prefix of the threads' sums: within each wave by shuffles,
+    // then over the 16 wave totals
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
     }
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    int run = part[threadIdx.x];
+    int run = incl - s;
+    for (int x = 0; x < wv; ++x) run += wsum[x];
+    if (threadIdx.x == 1023) *work_count = run + s;
     for (int L = lo; L < hi; ++L) {
         const int v = at(L);
         at(L) = run;
@@ -596,15 +614,28 @@ __global__ __launch_bounds__(256) void k_plan_scatter(const ProdDesc *__restrict
                                                       int quad, const int32_t *__restrict__ hist,
                                                       int32_t *__restrict__ work) {
     __shared__ int cur[NBUCKET];
-    const int total = tile_pre[nprod];
-    const int chunk = (total + nblk - 1) / nblk;
-    const int lo = blockIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
+    __shared__ int s_pre[PRE_LDS + 1];
+    const bool lds = nprod <= PRE_LDS;
+    if (lds)
+        for (int x = threadIdx.x; x <= nprod; x += 256) s_pre[x] = tile_pre[x];
     for (int q = threadIdx.x; q < NBUCKET; q += 256) cur[q] = hist[q * nblk + blockIdx.x];
     __syncthreads();
-    for (int g = lo + threadIdx.x; g < hi; g += 256) {
-        int p, t;
-        const int c = item_count(prods, tile_pre, morton, nprod, g, quad, p, t);
-        if (c >= 0) work[atomicAdd(&cur[bucket_of(c)], 1)] = tile_pre[p] + t;
+    const int32_t *pre = lds ? s_pre : tile_pre;
+    const int total = pre[nprod];
+    const int chunk = (total + nblk - 1) / nblk;
+    const int lo = blockIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
+    for (int base = lo; base < hi; base += 256 * PLAN_HIST_ITEMS) {
+        int c[PLAN_HIST_ITEMS], id[PLAN_HIST_ITEMS];
+#pragma unroll
+        for (int q = 0; q < PLAN_HIST_ITEMS; ++q) {
+            const int g = base + threadIdx.x + q * 256;
+            int p = 0, t = 0;
+            c[q] = g < hi ? item_count(prods, pre, morton, nprod, g, quad, p, t) : -1;
+            id[q] = c[q] >= 0 ? pre[p] + t : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < PLAN_HIST_ITEMS; ++q)
+            if (c[q] >= 0) work[atomicAdd(&cur[bucket_of(c[q])], 1)] = id[q];
     }
 }
 

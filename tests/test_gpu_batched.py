@@ -120,6 +120,27 @@ def test_batched_large_tables_match_solo(ctx):
     assert len(its) > 1  # the solves left the shared launches at different steps
 
 
+def test_batched_multiblock_sort_matches_solo(ctx):
+    """Tables of more than 16384 tiles are ordered by the multi-block sort
+    (per-block histograms, a scan, a scatter): a 132 x 132-tile solve and a
+    small one share such tables, and both must match their solo runs bitwise
+    (the small one runs alone on the one-launch front)."""
+    specs = [("kms", 4200, 0.8, 0, 1e-8), ("kms", 200, 0.7, 3, 1e-6)]
+    mats = [make(k, n, p, sd) for (k, n, p, sd, _) in specs]
+    solos = [solo(ctx, s, 32, tau) for s, (_, _, _, _, tau) in zip(mats, specs)]
+    solves = [ctx.solve_begin(dev(s), tau, 1e-10, 30, leaf=32, stagnation_stop=True)
+              for s, (_, _, _, _, tau) in zip(mats, specs)]
+    steps = 0
+    while ctx.solve_step(solves, 3) > 0:
+        steps += 1
+        assert steps < 40
+    for sv, (Ys, Zs, infos) in zip(solves, solos):
+        Y, Z, info = sv.finish()
+        assert info["status"] == infos["status"] and info["iterations"] == infos["iterations"]
+        np.testing.assert_array_equal(host(Y), Ys)
+        np.testing.assert_array_equal(host(Z), Zs)
+
+
 def test_continuous_batching_join_and_leave(ctx):
     mats = [make(k, n, p, sd) for (k, n, p, sd, _, _) in CASES]
     solos = [solo(ctx, s, leaf, tau) for s, (_, _, _, _, leaf, tau) in zip(mats, CASES)]
