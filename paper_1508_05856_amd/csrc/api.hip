@@ -562,9 +562,10 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
         TIMED(K_PYR, launch_pyramid_tab(p->ty, st));
         TRY(enqueue_front(ctx, p->tx, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
-        HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
+        const bool fuse = !p->damped && decide_builds_pyramid(p->tx);
+        HIPCHK(launch_ns_decide(p->solves, p->nsolve, fuse ? p->tx.prods : nullptr, st));
         if (p->damped) HIPCHK(launch_ns_map(kp, p->tx, p->leaf, st));
-        TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
+        if (!fuse) TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
         TRY(enqueue_front(ctx, p->tz, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tz, st));
         TIMED(K_PYR, launch_pyramid_tab(p->tz, st));
@@ -573,9 +574,10 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
     }
     TRY(enqueue_front(ctx, p->tx, p->leaf, gemm_prec(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tx, st));
-    HIPCHK(launch_ns_decide(p->solves, p->nsolve, st));
+    const bool fuse = !p->damped && decide_builds_pyramid(p->tx);
+    HIPCHK(launch_ns_decide(p->solves, p->nsolve, fuse ? p->tx.prods : nullptr, st));
     if (p->damped) HIPCHK(launch_ns_map(kp, p->tx, p->leaf, st));
-    TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
+    if (!fuse) TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
     TRY(enqueue_front(ctx, p->tyz, p->leaf, gemm_prec(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tyz, st));
     TIMED(K_PYR, launch_pyramid_tab(p->tyz, st));

@@ -180,7 +180,12 @@ bool front_small(const ProdTable &t, int leaf, int gprec);
 hipError_t launch_front_small(const ProdTable &t, int leaf, int gprec, hipStream_t st);
 hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st);  // pyramid of each product's C
 // Per solve: r_k, t_k, |R| records and the stop decision.
-hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, hipStream_t st);
+// With xpyr (the x products, one per solve in the solves' order), the block of
+// each solve still running after the decision also builds its x product's
+// norm pyramid, in place of launch_pyramid_tab; valid when
+// decide_builds_pyramid(x table) holds (every P <= 32).
+hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, const ProdDesc *xpyr, hipStream_t st);
+bool decide_builds_pyramid(const ProdTable &tx);
 // Transpose of each running product's A (current parity) into its C, with
 // C's leaf squared norms: tile (i,j) of C is tile (j,i) of A transposed.
 hipError_t launch_transpose_tab(int prec, const ProdTable &t, int leaf, hipStream_t st);

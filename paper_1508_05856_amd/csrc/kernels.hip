@@ -261,7 +261,7 @@ __device__ void pyramid_region(double *q, double *nrm, int P, int S, int nb, int
     const int G = S / R;  // regions per side
     const int gy = region / G, gx = region % G;
     const double *lvl = q + dev_level_off(P, S);
-    for (int e = threadIdx.x; e < R * R; e += 256) {
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
         const int r = e / R, c = e % R;
         const int64_t gr = (int64_t)gy * R + r, gc = (int64_t)gx * R + c;
         const double v = lvl[gr * S + gc];
@@ -836,8 +836,11 @@ hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t 
 // r_k >= 0.99 r_best, r_best = min(r_0..r_{k-1}), while r_best < 1/2 or
 // n |t_k| < 1/2 (stagnated, opt-in); k == maxit (not converged).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict__ solves) {
+__global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict__ solves,
+                                                    const ProdDesc *__restrict__ xpyr) {
     __shared__ double sh[16];
+    __shared__ double buf[32 * 32];
+    __shared__ int s_run;
     const SolveDesc &sd = solves[blockIdx.x];
     SolveState *st = sd.state;
     if (st->status != ST_RUNNING) return;
@@ -859,55 +862,64 @@ __global__ __launch_bounds__(1024) void k_ns_decide(const SolveDesc *__restrict_
     cx = block_sum<1024>(cx, sh);
     cy = block_sum<1024>(cy, sh);
     cz = block_sum<1024>(cz, sh);
-    if (threadIdx.x != 0) return;
-    const double r = sqrt(r2);
-    const double tk = ((double)sd.n - tr) / (double)sd.n;
-    sd.hist_r[k] = r;
-    sd.hist_t[k] = tk;
-    sd.hist_nR[3 * k] = (int64_t)cx;
-    if (sd.single) {
-        sd.hist_nR[3 * k + 1] = (int64_t)cy;
-        if (k > 0) sd.hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
-    } else if (k > 0) {
-        sd.hist_nR[3 * (k - 1) + 1] = (int64_t)cy;
-        sd.hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
-    }
-    st->triples += (int64_t)cx + (int64_t)cy + (int64_t)cz;
-    st->r = r;
-    st->t = tk;
-    if (k == 0) st->r0 = r;
-    int status = ST_RUNNING;
-    if (r < sd.tol) {
-        status = 0;  // SPAMM_OK
-    } else if (!isfinite(r) || r > 10.0 * fmax(st->r0, sqrt((double)sd.n))) {
-        status = -3;  // SPAMM_EDIVERGED
-    } else {
-        if (sd.stagnation_stop && k > 0) {
-            // progress against the best residual so far, counted only once
-            // every eigenvalue of an exact iterate is within 1/2 of 1 (best r
-            // below 1/2, or n |t_k| below 1/2 since exact iterates keep x in
-            // (0, 1]): there an exact update shrinks r by more than 2x, so a
-            // step gaining under 1% is the floor
-            const bool settled = st->r_prev < 0.5 || fabs(tk) * (double)sd.n < 0.5;
-            st->nondecrease = (settled && r >= 0.99 * st->r_prev) ? st->nondecrease + 1 : 0;
-            if (st->nondecrease >= 2) status = 2;  // SPAMM_STAGNATED
+    if (threadIdx.x == 0) {
+        const double r = sqrt(r2);
+        const double tk = ((double)sd.n - tr) / (double)sd.n;
+        sd.hist_r[k] = r;
+        sd.hist_t[k] = tk;
+        sd.hist_nR[3 * k] = (int64_t)cx;
+        if (sd.single) {
+            sd.hist_nR[3 * k + 1] = (int64_t)cy;
+            if (k > 0) sd.hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
+        } else if (k > 0) {
+            sd.hist_nR[3 * (k - 1) + 1] = (int64_t)cy;
+            sd.hist_nR[3 * (k - 1) + 2] = (int64_t)cz;
         }
-        if (status == ST_RUNNING) {
-            if (k == 0 || r < st->r_prev) st->r_prev = r;  // best residual so far
-            if (k == sd.maxit) status = 1;  // SPAMM_NOT_CONVERGED
+        st->triples += (int64_t)cx + (int64_t)cy + (int64_t)cz;
+        st->r = r;
+        st->t = tk;
+        if (k == 0) st->r0 = r;
+        int status = ST_RUNNING;
+        if (r < sd.tol) {
+            status = 0;  // SPAMM_OK
+        } else if (!isfinite(r) || r > 10.0 * fmax(st->r0, sqrt((double)sd.n))) {
+            status = -3;  // SPAMM_EDIVERGED
+        } else {
+            if (sd.stagnation_stop && k > 0) {
+                // progress against the best residual so far, counted only once
+                // every eigenvalue of an exact iterate is within 1/2 of 1 (best r
+                // below 1/2, or n |t_k| below 1/2 since exact iterates keep x in
+                // (0, 1]): there an exact update shrinks r by more than 2x, so a
+                // step gaining under 1% is the floor
+                const bool settled = st->r_prev < 0.5 || fabs(tk) * (double)sd.n < 0.5;
+                st->nondecrease = (settled && r >= 0.99 * st->r_prev) ? st->nondecrease + 1 : 0;
+                if (st->nondecrease >= 2) status = 2;  // SPAMM_STAGNATED
+            }
+            if (status == ST_RUNNING) {
+                if (k == 0 || r < st->r_prev) st->r_prev = r;  // best residual so far
+                if (k == sd.maxit) status = 1;  // SPAMM_NOT_CONVERGED
+            }
         }
+        // damped map (Sec. 4.2): scaling alpha(t) and stabilisation eps(t) of the
+        // trace error, both switched off once t_k < 0.1 (the sigmoids never reach
+        // 1 and 0 exactly; eps(0) alone would hold r above sqrt(n) 1.7e-11)
+        double alpha = 1.0, eps = 0.0;
+        if (sd.damped && tk >= 0.1) {
+            alpha = 1.0 + 1.85 / (1.0 + exp(-50.0 * (tk - 0.35)));
+            eps = 0.1 / (1.0 + exp(-75.0 * (tk - 0.30)));
+        }
+        st->alpha = alpha;
+        st->eps = eps;
+        st->status = status;
+        s_run = status == ST_RUNNING;
     }
-    // damped map (Sec. 4.2): scaling alpha(t) and stabilisation eps(t) of the
-    // trace error, both switched off once t_k < 0.1 (the sigmoids never reach
-    // 1 and 0 exactly; eps(0) alone would hold r above sqrt(n) 1.7e-11)
-    double alpha = 1.0, eps = 0.0;
-    if (sd.damped && tk >= 0.1) {
-        alpha = 1.0 + 1.85 / (1.0 + exp(-50.0 * (tk - 0.35)));
-        eps = 0.1 / (1.0 + exp(-75.0 * (tk - 0.30)));
-    }
-    st->alpha = alpha;
-    st->eps = eps;
-    st->status = status;
+    // the x product's pyramid (P <= 32: one region) for a solve still running
+    if (xpyr == nullptr) return;
+    __syncthreads();
+    if (!s_run) return;
+    const ProdDesc &d = xpyr[blockIdx.x];
+    const int par = prod_parity(d);
+    pyramid_region(d.qC[par], d.nrmC[par], d.P, d.P, d.nb, 1, 0, buf);
 }
 
 // Tile transpose, one workgroup per output tile, through LDS (b <= 64).
@@ -1004,10 +1016,12 @@ __global__ __launch_bounds__(64) void k_gather_states(const SolveDesc *__restric
     if (i < nsolve) out[i] = *solves[i].state;
 }
 
-hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, hipStream_t st) {
-    hipLaunchKernelGGL(k_ns_decide, dim3(nsolve), dim3(1024), 0, st, solves);
+hipError_t launch_ns_decide(const SolveDesc *solves, int nsolve, const ProdDesc *xpyr, hipStream_t st) {
+    hipLaunchKernelGGL(k_ns_decide, dim3(nsolve), dim3(1024), 0, st, solves, xpyr);
     return hipGetLastError();
 }
+
+bool decide_builds_pyramid(const ProdTable &tx) { return tx.total_pyr == tx.nprod && tx.total_pyr2 == 0; }
 
 hipError_t launch_ns_advance(const SolveDesc *solves, int nsolve, hipStream_t st) {
     hipLaunchKernelGGL(k_ns_advance, dim3((nsolve + 63) / 64), dim3(64), 0, st, solves, nsolve);
