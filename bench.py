@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--stagnation", action="store_true", help="c1: use the stagnation stop (default: literal)")
     p.add_argument("--damped", action="store_true", help="the damped map (alpha(t), eps(t) of the trace error)")
     p.add_argument("--cpu-sample-iters", type=int, default=8)
+    p.add_argument("--m", type=int, default=32, help="c3: lattice side, n = m^3 (16: the n = 4096 analogue, "
+                   "which the oracle solves whole for the CPU baseline)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--dump-launches", default=None, help="write per-launch (flops, ms) of the timed steps")
     p.add_argument("--compare-f64", action="store_true", help="also solve in FP64 and report the relative gap")
@@ -290,6 +292,29 @@ def run_serving(args):
     print(json.dumps(line), flush=True)
 
 
+ORACLE_FULL_MAX_N = 8192  # device-built inputs up to this n: the oracle solves them whole
+
+
+def cpu_baseline_full(s, leaf, args, mu_rel, stag, info, Y, Z):
+    """The oracle's whole solve of the same input and options (FP64 leaves
+    whatever the GPU precision), timed, with its agreement with the GPU
+    outputs beside it."""
+    import oracle
+    a = s.cpu().numpy()
+    tc = time.perf_counter()
+    ores = oracle.ns_sqrt(a, leaf, args.tau, args.tol, args.maxit, tau_s=args.tau_s, mu_rel=mu_rel,
+                          stagnation_stop=stag, damped=args.damped)
+    sec = time.perf_counter() - tc
+    Yh, Zh = Y.cpu().numpy(), Z.cpu().numpy()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / sec, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole solve (n = {a.shape[0]}, FP64 leaves): {sec:.1f} s",
+            "agreement": {"status": [info["status"], int(ores["status"])],
+                          "iterations": [info["iterations"], int(ores["iterations"])],
+                          "rel_Y": float(np.linalg.norm(Yh - ores["Y"]) / np.linalg.norm(ores["Y"])),
+                          "rel_Z": float(np.linalg.norm(Zh - ores["Z"]) / np.linalg.norm(ores["Z"]))}}
+
+
 def cpu_baseline_sampled_tiles(s, mu_rel, leaf, tau, info):
     """The oracle on a bounded sample of a problem too large for it whole: the
     pyramid of the regularised, scaled operand s' (all of it) and a sample of
@@ -471,7 +496,7 @@ def main():
     mu_rel = 0.0
     if args.workload == "c3":
         # n = 32768 ill-conditioned Gramian, built on the device (8 GiB in FP64)
-        cfg = inputs.config_c3_spec()
+        cfg = inputs.config_c3_spec(args.m)
         n, leaf = cfg["n"], cfg["leaf"]
         s_host = None
         s = inputs.gramian_device(inputs.gauss_positions(cfg["m"], cfg["h"], 0.1, 0, n), dev)
@@ -619,7 +644,9 @@ def main():
         },
     }
 
-    if not args.no_cpu_baseline and s_host is None:
+    if not args.no_cpu_baseline and s_host is None and n <= ORACLE_FULL_MAX_N:
+        line["cpu_baseline"] = cpu_baseline_full(s, leaf, args, mu_rel, stag, info, Y, Z)
+    elif not args.no_cpu_baseline and s_host is None:
         line["cpu_baseline"] = cpu_baseline_sampled_tiles(s, mu_rel, leaf, args.tau, info)
     elif not args.no_cpu_baseline:
         import oracle
