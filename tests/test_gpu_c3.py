@@ -128,3 +128,39 @@ def test_c3_ns_bf16x3_against_fp64(ctx, raw):
     print(f"  sampled columns of YZ - I: rms {col_rms:.2e}, in-loop r/sqrt(n) {i64['resid'] / np.sqrt(n):.2e}")
     # the exact residual of the sampled columns agrees with the in-loop one
     assert col_rms < 3.0 * i64["resid"] / np.sqrt(n)
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_c3_analogue_whole_solve_vs_oracle(ctx, prec):
+    """The same configuration (mu = 1e-4 c0, tau = 1e-9, tau_s = 0.01 tau,
+    damped map, stagnation stop, leaf 64) on the m = 12 lattice (n = 1728),
+    where the oracle runs the whole solve.  FP64 leaves: same status, update
+    count and residual history as the oracle, Y and Z to 1e-10.  BF16x3 leaves:
+    Y and Z within sqrt(kappa) 2^-16 of the oracle's FP64 roots (kappa <= 1 +
+    1/mu_rel), and a valid stop at a floor well below the stagnation guard's
+    1/2."""
+    cfg = inputs.config_c3_spec(12)
+    s = inputs.gauss_gramian(12, cfg["h"], 0.1, 0)
+    tau, tau_s = cfg["tau"], cfg["tau_s_rel"] * cfg["tau"]
+    print(f"n={s.shape[0]} tau={tau} damped mu_rel={cfg['mu_rel']} prec={prec}", flush=True)
+    Y, Z, info = ctx.ns_sqrt(torch.from_numpy(s).cuda(), tau, cfg["tol"], cfg["maxit"], leaf=cfg["leaf"], prec=prec,
+                             tau_s=tau_s, mu_rel=cfg["mu_rel"], stagnation_stop=True, damped=True,
+                             raise_on_error=False)
+    ores = oracle.ns_sqrt(s, cfg["leaf"], tau, cfg["tol"], cfg["maxit"], tau_s=tau_s, mu_rel=cfg["mu_rel"],
+                          stagnation_stop=True, damped=True)
+    Yh, Zh = Y.cpu().numpy(), Z.cpu().numpy()
+    ey = np.linalg.norm(Yh - ores["Y"]) / np.linalg.norm(ores["Y"])
+    ez = np.linalg.norm(Zh - ores["Z"]) / np.linalg.norm(ores["Z"])
+    print(f"status {info['status']} vs {ores['status']}, updates {info['iterations']} vs {ores['iterations']}, "
+          f"relY {ey:.2e} relZ {ez:.2e}")
+    if prec == "f64":
+        assert info["status"] == ores["status"] and info["iterations"] == ores["iterations"]
+        r, _, _ = ctx.ns_history()
+        k = ores["iterations"]
+        np.testing.assert_allclose(r[:k + 1], ores["r"][:k + 1], rtol=1e-9)
+        assert ey <= 1e-10 and ez <= 1e-10
+    else:
+        bound = np.sqrt(1.0 + 1.0 / cfg["mu_rel"]) * 2.0 ** -16
+        assert info["status"] in (0, 2)
+        assert ey <= bound and ez <= bound
+        assert info["resid"] < 0.05
