@@ -279,7 +279,10 @@ int spamm_set_graphs(spamm_ctx *ctx, int enable);
 /* Launch timing, for measurement.  While enabled, every leaf-product launch
  * (kind 0), cull launch (kind 1) and norm-pyramid launch (kind 2) enqueued
  * through this context is bracketed by a pair of HIP events recorded on the
- * same stream.  Events come from a fixed pool created at enable time (no
+ * same stream.  For product tables of at most 1024 tiles the cull launch also
+ * orders the work and writes the job list, and with the plain map the
+ * pyramid of such a solve's x product is built inside the (untimed) stop
+ * decision.  Events come from a fixed pool created at enable time (no
  * allocation while solving); when it is exhausted recording stops silently.
  * spamm_profile_enable(ctx, 1) also clears earlier records; 0 disables. */
 int spamm_profile_enable(spamm_ctx *ctx, int enable);
