@@ -62,7 +62,7 @@ def test_single_channel_matches_oracle(ctx, case):
     assert rel(Y.cpu().numpy(), o["Y"]) <= 1e-12 and rel(Z.cpu().numpy(), o["Z"]) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
 def test_single_and_dual_in_one_step_match_solo(ctx, prec):
     mats = [inputs.kms(300, 0.7), inputs.gauss_gramian(8, 1.0), inputs.kms(500, 0.85), inputs.gauss_gramian(6, 1.2)]
     single = [True, False, True, False]
@@ -78,12 +78,14 @@ def test_single_and_dual_in_one_step_match_solo(ctx, prec):
         assert torch.equal(Y, Ys) and torch.equal(Z, Zs)
 
 
-def test_single_channel_bf16x3_error(ctx):
+@pytest.mark.parametrize("leaf", [32, 64])
+def test_single_channel_bf16x3_error(ctx, leaf):
+    """Leaf 32 runs the one-tile BF16x3 kernel, leaf 64 the quad kernel."""
     s = inputs.kms(512, 0.7)
     w = np.linalg.eigvalsh(s)
     bound = np.sqrt(w[-1] / w[0]) * 2.0 ** -16
-    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-8, 1e-5, 40, leaf=32, prec="bf16x3", stagnation_stop=True, single=True)
-    o = oracle.ns_sqrt(s, 32, 1e-8, 1e-5, 40, stagnation_stop=True, single=True)
+    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-8, 1e-5, 40, leaf=leaf, prec="bf16x3", stagnation_stop=True, single=True)
+    o = oracle.ns_sqrt(s, leaf, 1e-8, 1e-5, 40, stagnation_stop=True, single=True)
     ey, ez = rel(Y.cpu().numpy(), o["Y"]), rel(Z.cpu().numpy(), o["Z"])
     print(f"single bf16x3: relY {ey:.2e} relZ {ez:.2e} (bound {bound:.2e})")
     assert ey <= bound and ez <= bound
