@@ -113,6 +113,31 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
                    double tau, int leaf, int prec, int32_t *triples, int64_t cap, spamm_stats *stats,
                    void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * product as spamm_multiply, C = A (x)_tau B, with the same kernels and so
+ * the same results, that allocates nothing.  Every working buffer (tiles,
+ * norm pyramids, task list, product table) is carved from a static device
+ * array of SPAMM_NOALLOC_BYTES per GPU, located when a context is created on
+ * that GPU and held until the process ends.
+ *
+ * A, B: DEVICE inputs; C: DEVICE output (n x n, leading dimension ld >= n;
+ *   C may not alias A or B).  tau, leaf, prec as spamm_multiply.
+ * No statistics or triples, and no synchronisation: the work is enqueued on
+ * `stream` and the call returns.
+ * Errors: EINVAL for invalid arguments and for sizes whose buffers exceed
+ *   the static array (about n <= 1100 for FP64 tiles, n <= 1500 for FP32 and
+ *   BF16x3 tiles; the message names the bytes needed); EHIP.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (what must start at zero is cleared by the call): calls that
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.
+ */
+#define SPAMM_NOALLOC_BYTES 33554432u /* 32 MiB */
+int spamm_multiply_noalloc(spamm_ctx *ctx, const double *A, const double *B, double *C, int64_t n, int64_t ld,
+                           double tau, int leaf, int prec, void *stream);
+
 typedef struct {
     int leaf;            /* N_b in {16, 32, 64}; 0 = 32                                    */
     int prec;            /* spamm_prec                                                     */

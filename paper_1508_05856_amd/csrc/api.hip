@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,13 @@
 #include "spamm.h"
 
 using namespace spk;
+
+// Static scratch of the allocation-free product (spamm_multiply_noalloc).
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code the name is only a stand-in for the symbol: each device's copy
+// is located once, with that device current, by hipGetSymbolAddress when a
+// context is created on it, and only that address is passed to kernels.
+static __device__ __align__(256) char scratch[SPAMM_NOALLOC_BYTES];
 
 namespace {
 
@@ -47,6 +55,25 @@ int fail(int code, const char *fmt, ...) {
         int s_ = (x);          \
         if (s_ < 0) return s_; \
     } while (0)
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+// Locates the current device's copy of `scratch` (once per device).
+int scratch_setup(int device, void **out) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(SPAMM_EINVAL, "device %d beyond %d", device, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SPAMM_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_dev[device] = ptr;
+    }
+    *out = g_scratch_dev[device];
+    return SPAMM_OK;
+}
 
 bool valid_leaf(int b) { return b == 16 || b == 32 || b == 64; }
 bool valid_prec(int p) { return p == SPAMM_F64 || p == SPAMM_F32 || p == SPAMM_BF16X3; }
@@ -128,6 +155,7 @@ struct spamm_ctx {
     // the first, so that the plans of one step run concurrently
     std::vector<hipStream_t> xstream;
     std::vector<hipEvent_t> xdone;
+    void *scratch = nullptr;              // this device's copy of the static scratch
 };
 
 struct spamm_solve {
@@ -225,9 +253,10 @@ struct TableSizes {
     int nprod, total_cull, total_tiles, total_pyr, total_pyr2, total_quads, max_nb, hist_blocks;
 };
 
-TableSizes table_sizes(const std::vector<ProdDesc> &prods) {
-    TableSizes z{(int)prods.size(), 0, 0, 0, 0, 0, 0, 0};
-    for (const ProdDesc &d : prods) {
+TableSizes table_sizes(const ProdDesc *prods, int nprod) {
+    TableSizes z{nprod, 0, 0, 0, 0, 0, 0, 0};
+    for (int p = 0; p < nprod; ++p) {
+        const ProdDesc &d = prods[p];
         z.total_cull += (d.nb * d.nb + 3) / 4;
         z.total_tiles += d.nb * d.nb;
         z.total_quads += ((d.nb + 1) / 2) * ((d.nb + 1) / 2);
@@ -242,8 +271,8 @@ TableSizes table_sizes(const std::vector<ProdDesc> &prods) {
 
 // Lays out one table in `c` (device addresses) and, when `host` is non-null,
 // writes its contents into the host staging image at the same offsets.
-ProdTable layout_table(Carve &c, const std::vector<ProdDesc> &prods, std::vector<char> *host) {
-    const TableSizes z = table_sizes(prods);
+ProdTable layout_table(Carve &c, const ProdDesc *prods, int nprod, std::vector<char> *host) {
+    const TableSizes z = table_sizes(prods, nprod);
     ProdTable t{};
     const size_t o_prods = c.off;
     t.prods = c.take<ProdDesc>(z.nprod);
@@ -272,7 +301,7 @@ ProdTable layout_table(Carve &c, const std::vector<ProdDesc> &prods, std::vector
     if (host) {
         if (host->size() < c.off) host->resize(c.off);
         char *h = host->data();
-        std::memcpy(h + o_prods, prods.data(), prods.size() * sizeof(ProdDesc));
+        std::memcpy(h + o_prods, prods, (size_t)nprod * sizeof(ProdDesc));
         int32_t *cull = (int32_t *)(h + o_cull), *tile = (int32_t *)(h + o_tile);
         int32_t *pyr = (int32_t *)(h + o_pyr), *pyr2 = (int32_t *)(h + o_pyr2);
         int32_t *mort = (int32_t *)(h + o_mort);
@@ -479,13 +508,13 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
         sd.push_back(solve_desc(s));
     }
     Carve sizing{nullptr, 0};
-    layout_table(sizing, px, nullptr);
+    layout_table(sizing, px.data(), (int)px.size(), nullptr);
     if (single) {
-        layout_table(sizing, pt, nullptr);
-        layout_table(sizing, py, nullptr);
-        layout_table(sizing, pz, nullptr);
+        layout_table(sizing, pt.data(), (int)pt.size(), nullptr);
+        layout_table(sizing, py.data(), (int)py.size(), nullptr);
+        layout_table(sizing, pz.data(), (int)pz.size(), nullptr);
     } else {
-        layout_table(sizing, pyz, nullptr);
+        layout_table(sizing, pyz.data(), (int)pyz.size(), nullptr);
     }
     sizing.take<SolveDesc>(sd.size());
     sizing.take<SolveState>(sd.size());
@@ -507,13 +536,13 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
     }
     std::vector<char> image;
     Carve c{p->mem, 0};
-    p->tx = layout_table(c, px, &image);
+    p->tx = layout_table(c, px.data(), (int)px.size(), &image);
     if (single) {
-        p->tt = layout_table(c, pt, &image);
-        p->ty = layout_table(c, py, &image);
-        p->tz = layout_table(c, pz, &image);
+        p->tt = layout_table(c, pt.data(), (int)pt.size(), &image);
+        p->ty = layout_table(c, py.data(), (int)py.size(), &image);
+        p->tz = layout_table(c, pz.data(), (int)pz.size(), &image);
     } else {
-        p->tyz = layout_table(c, pyz, &image);
+        p->tyz = layout_table(c, pyz.data(), (int)pyz.size(), &image);
     }
     const size_t o_sd = c.off;
     p->solves = c.take<SolveDesc>(sd.size());
@@ -690,6 +719,40 @@ spamm_ns_opts default_opts(const spamm_ns_opts *opts) {
     return o;
 }
 
+// C = A (x)_tau B on tiles T[0], T[1] -> T[2] (no solve: always runs, parity 0).
+ProdDesc plain_product(const Geom &g, double tau, void *const *T, double *const *q, double *const *nr, int32_t *cnt,
+                       int32_t *kidx) {
+    ProdDesc d{};
+    d.n = g.n;
+    d.nb = g.nb;
+    d.P = g.P;
+    d.tau = tau;
+    d.A[0] = d.A[1] = T[0];
+    d.B[0] = d.B[1] = T[1];
+    d.C[0] = d.C[1] = T[2];
+    d.nrmA[0] = d.nrmA[1] = nr[0];
+    d.nrmB[0] = d.nrmB[1] = nr[1];
+    d.rootA[0] = d.rootA[1] = root_of(q[0], g.P);
+    d.rootB[0] = d.rootB[1] = root_of(q[1], g.P);
+    d.qC[0] = d.qC[1] = q[2];
+    d.nrmC[0] = d.nrmC[1] = nr[2];
+    d.cnt = cnt;
+    d.kidx = kidx;
+    d.part = nullptr;
+    d.state = nullptr;
+    return d;
+}
+
+int validate_multiply(spamm_ctx *ctx, const double *A, const double *B, const double *C, int64_t n, int64_t ld,
+                      double tau, int leaf, int prec) {
+    TRY(validate_common(ctx, A, n, ld, leaf));
+    if (!B || !C) return fail(SPAMM_EINVAL, "NULL matrix pointer");
+    if (!(tau >= 0.0) || std::isinf(tau)) return fail(SPAMM_EINVAL, "tau must be finite and >= 0");
+    if (!valid_prec(prec)) return fail(SPAMM_EINVAL, "unknown precision %d", prec);
+    if (prec == SPAMM_BF16X3 && leaf == 16) return fail(SPAMM_EINVAL, "BF16x3 leaves need leaf 32 or 64");
+    return SPAMM_OK;
+}
+
 void fill_result(const spamm_solve *s, spamm_ns_result *res) {
     if (!res) return;
     const SolveState &h = s->host_state;
@@ -714,8 +777,11 @@ int spamm_create(spamm_ctx **out, int device) {
     HIPCHK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(SPAMM_EINVAL, "device %d out of range [0,%d)", device, count);
     HIPCHK(hipSetDevice(device));
+    void *scr = nullptr;
+    TRY(scratch_setup(device, &scr));
     spamm_ctx *ctx = new spamm_ctx();
     ctx->device = device;
+    ctx->scratch = scr;
     hipError_t e = hipHostMalloc((void **)&ctx->pinned, 64 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete ctx;
@@ -787,11 +853,7 @@ int spamm_norms(spamm_ctx *ctx, const double *A, int64_t n, int64_t ld, int leaf
 int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, int64_t n, int64_t ld,
                    double tau, int leaf, int prec, int32_t *triples, int64_t cap, spamm_stats *stats,
                    void *stream) {
-    TRY(validate_common(ctx, A, n, ld, leaf));
-    if (!B || !C) return fail(SPAMM_EINVAL, "NULL matrix pointer");
-    if (!(tau >= 0.0) || std::isinf(tau)) return fail(SPAMM_EINVAL, "tau must be finite and >= 0");
-    if (!valid_prec(prec)) return fail(SPAMM_EINVAL, "unknown precision %d", prec);
-    if (prec == SPAMM_BF16X3 && leaf == 16) return fail(SPAMM_EINVAL, "BF16x3 leaves need leaf 32 or 64");
+    TRY(validate_multiply(ctx, A, B, C, n, ld, tau, leaf, prec));
     if (triples && cap < 0) return fail(SPAMM_EINVAL, "negative triple capacity");
     TRY(enter(ctx));
     hipStream_t st = (hipStream_t)stream;
@@ -816,31 +878,15 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     HIPCHK(launch_ingest(kp, B, ld, 0.0, 1.0, g, ctx->buf[S_T1], q[1], st));
     TIMED(K_PYR, launch_pyramid(g, q[0], nr[0], q[1], nr[1], 2, st));
 
-    ProdDesc d{};
-    d.n = n;
-    d.nb = g.nb;
-    d.P = g.P;
-    d.tau = tau;
-    d.A[0] = d.A[1] = ctx->buf[S_T0];
-    d.B[0] = d.B[1] = ctx->buf[S_T1];
-    d.C[0] = d.C[1] = ctx->buf[S_T2];
-    d.nrmA[0] = d.nrmA[1] = nr[0];
-    d.nrmB[0] = d.nrmB[1] = nr[1];
-    d.rootA[0] = d.rootA[1] = root_of(q[0], g.P);
-    d.rootB[0] = d.rootB[1] = root_of(q[1], g.P);
-    d.qC[0] = d.qC[1] = q[2];
-    d.nrmC[0] = d.nrmC[1] = nr[2];
-    d.cnt = slot_ptr<int32_t>(ctx, S_CNT);
-    d.kidx = slot_ptr<int32_t>(ctx, S_KIDX);
-    d.part = nullptr;
-    d.state = nullptr;
+    void *T[3] = {ctx->buf[S_T0], ctx->buf[S_T1], ctx->buf[S_T2]};
+    const ProdDesc d = plain_product(g, tau, T, q, nr, slot_ptr<int32_t>(ctx, S_CNT), slot_ptr<int32_t>(ctx, S_KIDX));
     std::vector<ProdDesc> prods{d};
     Carve sizing{nullptr, 0};
-    layout_table(sizing, prods, nullptr);
+    layout_table(sizing, prods.data(), (int)prods.size(), nullptr);
     TRY(ensure(ctx, S_TAB, sizing.off));
     std::vector<char> image;
     Carve c{(char *)ctx->buf[S_TAB], 0};
-    ProdTable t = layout_table(c, prods, &image);
+    ProdTable t = layout_table(c, prods.data(), (int)prods.size(), &image);
     image.resize(c.off);
     HIPCHK(hipMemcpyAsync(ctx->buf[S_TAB], image.data(), image.size(), hipMemcpyHostToDevice, st));
     TRY(enqueue_front(ctx, t, leaf, gemm_prec(prec), st));
@@ -875,6 +921,42 @@ int spamm_multiply(spamm_ctx *ctx, const double *A, const double *B, double *C, 
     // the host staging image must outlive its copy
     HIPCHK(hipStreamSynchronize(st));
     return status;
+}
+
+int spamm_multiply_noalloc(spamm_ctx *ctx, const double *A, const double *B, double *C, int64_t n, int64_t ld,
+                           double tau, int leaf, int prec, void *stream) {
+    TRY(validate_multiply(ctx, A, B, C, n, ld, tau, leaf, prec));
+    if (!ctx->scratch) return fail(SPAMM_EHIP, "the static scratch of device %d was not located", ctx->device);
+    const Geom g = make_geom(n, leaf);
+    const size_t nb2 = (size_t)g.nb * g.nb;
+    // every buffer of spamm_multiply, carved from this device's static scratch
+    Carve c{(char *)ctx->scratch, 0};
+    void *T[3];
+    double *q[3], *nr[3];
+    for (int m = 0; m < 3; ++m) T[m] = c.take<char>(nb2 * g.b * g.b * elt_size(prec));
+    for (int m = 0; m < 3; ++m) q[m] = c.take<double>((size_t)pyr_len(g.P));
+    for (int m = 0; m < 3; ++m) nr[m] = c.take<double>(2 * nb2);
+    int32_t *cnt = c.take<int32_t>(nb2);
+    int32_t *kidx = c.take<int32_t>(nb2 * g.nb);
+    const ProdDesc d = plain_product(g, tau, T, q, nr, cnt, kidx);
+    const ProdTable t = layout_table(c, &d, 1, nullptr);
+    if (c.off > (size_t)SPAMM_NOALLOC_BYTES)
+        return fail(SPAMM_EINVAL, "n = %lld at leaf %d needs %zu bytes of scratch, more than the static %zu",
+                    (long long)n, leaf, c.off, (size_t)SPAMM_NOALLOC_BYTES);
+    TRY(enter(ctx));
+    hipStream_t st = (hipStream_t)stream;
+    const int kp = kernel_prec(prec);
+    // the array keeps the previous call's contents: the leaf levels of the
+    // pyramids (virtual blocks must read 0) are cleared by a kernel
+    for (int m = 0; m < 3; ++m) HIPCHK(launch_fill_zero(q[m], (int64_t)g.P * g.P, st));
+    HIPCHK(launch_ingest(kp, A, ld, 0.0, 1.0, g, T[0], q[0], st));
+    HIPCHK(launch_ingest(kp, B, ld, 0.0, 1.0, g, T[1], q[1], st));
+    TIMED(K_PYR, launch_pyramid(g, q[0], nr[0], q[1], nr[1], 2, st));
+    HIPCHK(launch_table_one(d, t, st));
+    TRY(enqueue_front(ctx, t, leaf, gemm_prec(prec), st));
+    TIMED(K_GEMM, launch_gemm_tab(gemm_prec(prec), leaf, t, st));
+    HIPCHK(launch_egress(kp, g, T[2], C, ld, 1.0, 0, st));
+    return SPAMM_OK;
 }
 
 size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit, int single) {

@@ -165,6 +165,12 @@ hipError_t launch_shift_copy(const double *src, double *dst, int64_t n, int64_t 
 hipError_t launch_transpose_dense(const double *src, double *dst, int64_t n, int64_t ld, hipStream_t st);
 hipError_t launch_sym_part(const double *src, double *dst, int64_t n, int64_t ld, hipStream_t st);
 
+// One-product table set up on the device (descriptor, prefixes, Morton
+// order), for callers that cannot stage a table image from the host; and a
+// fill kernel clearing doubles (in place of a memset node).
+hipError_t launch_table_one(const ProdDesc &d, const ProdTable &t, hipStream_t st);
+hipError_t launch_fill_zero(double *p, int64_t count, hipStream_t st);
+
 // Batched stages over a product table.
 hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st);
 // Longest-first job list for the leaf products of precision gprec on leaf

@@ -54,6 +54,85 @@ void tile_order(int nb, int32_t *order) {
 }
 
 // ---------------------------------------------------------------------------
+// Device-side set-up of a one-product table (the allocation-free product):
+// the product descriptor, the prefix arrays and the Morton order of its
+// nb x nb tiles, the same order tile_order lists on the host, built in
+// chunks of 4096 Morton codes with a block scan for the compaction.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_table_one(ProdDesc d, ProdTable t) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nb = d.nb, P = d.P;
+    if (tid == 0) {
+        *const_cast<ProdDesc *>(t.prods) = d;
+        const int32_t nb2 = nb * nb;
+        int32_t *cull = const_cast<int32_t *>(t.cull_pre), *tile = const_cast<int32_t *>(t.tile_pre);
+        int32_t *pyr = const_cast<int32_t *>(t.pyr_pre), *pyr2 = const_cast<int32_t *>(t.pyr2_pre);
+        cull[0] = tile[0] = pyr[0] = pyr2[0] = 0;
+        cull[1] = (nb2 + 3) / 4;
+        tile[1] = nb2;
+        pyr[1] = P <= 32 ? 1 : (P / 32) * (P / 32);
+        pyr2[1] = P > 32 ? 1 : 0;
+        carry = 0;
+    }
+    __syncthreads();
+    int32_t *morton = const_cast<int32_t *>(t.morton);
+    const int64_t PP = (int64_t)P * P;
+    for (int64_t base = 0; base < PP; base += 4 * 1024) {
+        int idx[4], valid[4], mine = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t z = base + 4 * tid + u;
+            int i = 0, j = 0;
+            for (int bit = 0; (1 << bit) < P; ++bit) {
+                j |= (int)((z >> (2 * bit)) & 1) << bit;
+                i |= (int)((z >> (2 * bit + 1)) & 1) << bit;
+            }
+            valid[u] = (z < PP && i < nb && j < nb) ? 1 : 0;
+            idx[u] = i * nb + j;
+            mine += valid[u];
+        }
+        int incl = mine;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int pos = carry + incl - mine;
+        for (int x = 0; x < w; ++x) pos += wsum[x];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (valid[u]) morton[pos++] = idx[u];
+        __syncthreads();
+        if (tid == 0) {
+            int tot = 0;
+            for (int x = 0; x < 16; ++x) tot += wsum[x];
+            carry += tot;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_table_one(const ProdDesc &d, const ProdTable &t, hipStream_t st) {
+    hipLaunchKernelGGL(k_table_one, dim3(1), dim3(1024), 0, st, d, t);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(double *__restrict__ p, int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) p[e] = 0.0;
+}
+
+hipError_t launch_fill_zero(double *p, int64_t count, hipStream_t st) {
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)(blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024)), dim3(256), 0,
+                       st, p, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Input checks: max |s - s^T|, max |s|, and a non-finite flag, per 32x32 block
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_check_input(const double *__restrict__ s, int64_t n, int64_t ld,

@@ -28,7 +28,8 @@ STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", STAGNATED: "STAGNATED"
 EXPORTS = ("spamm_create", "spamm_destroy", "spamm_last_error", "spamm_pyramid_len", "spamm_norms",
            "spamm_multiply", "ns_sqrt", "spamm_ns_history", "spamm_solve_footprint", "spamm_solve_begin",
            "spamm_solve_step", "spamm_solve_poll", "spamm_solve_finish", "spamm_set_graphs", "spamm_profile_enable",
-           "spamm_profile_read", "spamm_profile_reset", "spamm_solve_triples", "spamm_product_rep")
+           "spamm_profile_read", "spamm_profile_reset", "spamm_solve_triples", "spamm_product_rep",
+           "spamm_multiply_noalloc")
 MAX_SLICES = 16
 KIND_GEMM, KIND_CULL, KIND_PYRAMID = 0, 1, 2
 
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.spamm_norms.argtypes = [vp, vp, i64, i64, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double), vp]
         lib.spamm_multiply.argtypes = [vp, vp, vp, vp, i64, i64, dbl, ctypes.c_int, ctypes.c_int, i32p, i64,
                                        ctypes.POINTER(Stats), vp]
+        lib.spamm_multiply_noalloc.argtypes = [vp, vp, vp, vp, i64, i64, dbl, ctypes.c_int, ctypes.c_int, vp]
+        lib.spamm_multiply_noalloc.restype = ctypes.c_int
         lib.ns_sqrt.argtypes = [vp, vp, vp, vp, i64, i64, dbl, dbl, ctypes.c_int, ctypes.POINTER(NsOpts),
                                 ctypes.POINTER(NsResult), vp]
         lib.spamm_ns_history.argtypes = [vp, vp, vp, vp, ctypes.c_int]
@@ -201,6 +204,25 @@ class Context:
         if trip is not None:
             trip = trip[:st.retained]
         return C, stats, trip
+
+    def spamm_multiply_noalloc(self, A: torch.Tensor, B: torch.Tensor, tau: float, leaf: int, prec="f64",
+                               C: torch.Tensor | None = None) -> torch.Tensor:
+        """C = A (x)_tau B through the allocation-free entry point (static
+        device scratch; enqueued on the current stream, not synchronised).
+        C must be preallocated by callers that cannot allocate."""
+        pa, ld = _mat(A, "A")
+        pb, ldb = _mat(B, "B")
+        if B.shape != A.shape or ldb != ld:
+            raise ValueError("A and B must have the same shape and leading dimension")
+        if C is None:
+            C = torch.empty_like(A)
+        pc, ldc = _mat(C, "C")
+        if ldc != ld:
+            raise ValueError("C must share A's leading dimension")
+        _check(self.lib.spamm_multiply_noalloc(self.handle, pa, pb, pc, A.shape[0], ld, float(tau), leaf,
+                                               _PREC[prec] if isinstance(prec, str) else int(prec),
+                                               _stream_ptr(A.device)))
+        return C
 
     def ns_sqrt(self, s: torch.Tensor, tau: float, tol: float, maxit: int, leaf: int = 32, prec="f64",
                 tau_s: float = -1.0, mu_rel: float = 0.0, stagnation_stop: bool = False, damped: bool = False,
