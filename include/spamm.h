@@ -53,8 +53,15 @@ typedef enum {
 typedef enum {
     SPAMM_F64 = 0,    /* FP64 tiles, FP64 MFMA                                       */
     SPAMM_F32 = 1,    /* FP32 tiles, FP32 MFMA, FP32 accumulation                    */
-    SPAMM_BF16X3 = 2  /* FP32 tiles; each product a_hi b_hi + a_hi b_lo + a_lo b_hi
-                         on BF16 MFMA with FP32 accumulation (a = a_hi + a_lo)       */
+    SPAMM_BF16X3 = 2, /* FP32 tiles; each product a_hi b_hi + a_hi b_lo + a_lo b_hi
+                         on BF16 MFMA with FP32 accumulation (a = a_hi + a_lo, two
+                         bf16 pieces: O(2^-16) relative error per product)          */
+    SPAMM_BF16X6 = 3  /* FP32 tiles split into three bf16 pieces a = a_hi + a_mid + a_lo
+                         (exact for every FP32 value); the product of two 32-k
+                         slices is the six terms down to 2^-16 relative (a_lo b_hi,
+                         a_hi b_lo, a_mid b_mid, a_mid b_hi, a_hi b_mid, a_hi b_hi,
+                         in that order) on BF16 MFMA summed in FP32, and the slice
+                         sums are accumulated in FP64: FP32 storage is the error */
 } spamm_prec;
 
 typedef struct spamm_ctx spamm_ctx;
@@ -64,7 +71,8 @@ typedef struct spamm_ctx spamm_ctx;
  * ctx or bad device), EHIP. */
 int spamm_create(spamm_ctx **ctx, int device);
 
-/* Release the context and all its device memory (synchronises the device). */
+/* Release the context and all its device memory, pooled memory and solves
+ * begun and not finished included (synchronises the device). */
 int spamm_destroy(spamm_ctx *ctx);
 
 /* Thread-local text describing the most recent status < 0 on this thread. */
@@ -212,9 +220,13 @@ typedef struct spamm_solve spamm_solve;
  * arguments. */
 size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit, int single);
 
-/* Checks s (as ns_sqrt), scales it, allocates the solve's device memory and
- * sets y_0 = s', z_0 = I_n.  s may be freed once this returns (synchronises).
- * *out receives the solve; errors as ns_sqrt (EINVAL, ENOMEM, EHIP). */
+/* Checks s (as ns_sqrt), scales it, takes the solve's device memory from the
+ * context's pool (allocating only when no pooled block fits) and sets
+ * y_0 = s', z_0 = I_n.  It also reserves in the pool the tables and pinned
+ * read-back buffer of a step over every unfinished solve of its (precision,
+ * leaf, channel) group on this context, so steps and finishes need no
+ * allocation.  s may be freed once this returns (synchronises).  *out
+ * receives the solve; errors as ns_sqrt (EINVAL, ENOMEM, EHIP). */
 int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, double tau, double tol, int maxit,
                       const spamm_ns_opts *opts, spamm_solve **out, void *stream);
 
@@ -223,9 +235,12 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
  * launches per (precision, leaf, channel) group; the stop tests run on the
  * device.  The groups run concurrently on streams of the context that start
  * after the work already on `stream`, and `stream` waits for all of them.
- * Finished solves in the list are skipped; a solve may appear once.
- * Synchronises once.  Returns the number of solves of the list still running,
- * or < 0 on error (EINVAL for a NULL, repeated or foreign solve). */
+ * Stopped solves in the list do no work; a solve may appear once.  The
+ * tables and captured graph of a group are rebuilt only when its list of
+ * unfinished solves changes (a solve joins or is finished), from memory
+ * reserved by spamm_solve_begin.  Synchronises once.  Returns the number of
+ * solves of the list still running, or < 0 on error (EINVAL for a NULL,
+ * repeated or foreign solve). */
 int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int iterations, void *stream);
 
 /* Host-side state after the last step: *done = 1 once stopped; res as for
@@ -233,8 +248,9 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
 int spamm_solve_poll(spamm_solve *solve, int *done, spamm_ns_result *res);
 
 /* Writes Y = sqrt(c) y_k and Z = z_k / sqrt(c) (either may be NULL), records
- * the solve's history for spamm_ns_history, frees the solve and returns its
- * status (NOT_CONVERGED if it was still running).  Synchronises. */
+ * the solve's history for spamm_ns_history, releases the solve (its device
+ * memory and its tables go back to the context's pool, nothing is freed) and
+ * returns its status (NOT_CONVERGED if it was still running).  Synchronises. */
 int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *solve, double *Y, double *Z, int64_t ld, void *stream);
 
 /* Retained (i, j, k) leaf triples of the most recent product of one channel
@@ -320,6 +336,13 @@ int spamm_profile_read(spamm_ctx *ctx, int kind, double *ms, int cap);
 
 /* Forget the recorded launches (the pool is reused). */
 int spamm_profile_reset(spamm_ctx *ctx);
+
+/* Device and pinned host allocations this context has made so far: scratch
+ * growth, solve arenas, plan tables and read-back buffers.  Memory of
+ * finished solves and dropped tables is pooled and reused, not freed, so a
+ * warm context steps and finishes solves without adding to this count.
+ * Returns -1 for a NULL context. */
+int64_t spamm_alloc_count(spamm_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -60,5 +60,17 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_probe(src: str) -> str:
+    """Compiles a stand-alone HIP test probe (source next to its test) into an
+    executable beside it."""
+    exe = os.path.splitext(src)[0]
+    cmd = [_hipcc(), "-O2", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", src, "-o", exe]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{p.stdout}{p.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

@@ -7,6 +7,13 @@
 // products, stop decision, pyramid; the same for the (y, z) update), and the
 // stop decision is taken on the device, so the host synchronises once per
 // step, not once per product.  ns_sqrt is begin + steps + finish.
+//
+// Device memory of the solve engine is recycled, not freed: solve arenas,
+// plan tables and pinned read-back buffers return to pools of the context
+// when a solve finishes or a plan is dropped, and are taken from them again
+// (best fit).  spamm_solve_begin reserves what the solve's group will need,
+// so once a context is warm, steps and finishes allocate and free nothing
+// (hipFree would also synchronise the whole device, stalling other streams).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -76,11 +83,14 @@ int scratch_setup(int device, void **out) {
 }
 
 bool valid_leaf(int b) { return b == 16 || b == 32 || b == 64; }
-bool valid_prec(int p) { return p == SPAMM_F64 || p == SPAMM_F32 || p == SPAMM_BF16X3; }
+bool valid_prec(int p) { return p == SPAMM_F64 || p == SPAMM_F32 || p == SPAMM_BF16X3 || p == SPAMM_BF16X6; }
+bool split_bf16(int p) { return p == SPAMM_BF16X3 || p == SPAMM_BF16X6; }
 size_t elt_size(int prec) { return prec == SPAMM_F64 ? 8 : 4; }
-// storage type of the tiles: BF16x3 keeps FP32 operands and splits them inside the leaf product
+// storage type of the tiles: the split-bf16 modes keep FP32 operands and split them inside the leaf product
 int kernel_prec(int prec) { return prec == SPAMM_F64 ? P_F64 : P_F32; }
-int gemm_prec(int prec) { return prec == SPAMM_F64 ? P_F64 : (prec == SPAMM_BF16X3 ? P_BF16X3 : P_F32); }
+int gemm_prec(int prec) {
+    return prec == SPAMM_F64 ? P_F64 : (prec == SPAMM_BF16X3 ? P_BF16X3 : (prec == SPAMM_BF16X6 ? P_BF16X6 : P_F32));
+}
 constexpr int MAX_NB = 1024;  // the pyramid's two passes cover P <= 1024
 static_assert(MAX_NB <= QUAD_NB_MAX, "the quad kernel's k union covers every supported nb");
 
@@ -116,6 +126,12 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
+// A device (or pinned host) allocation kept in a context's pool.
+struct Block {
+    char *p = nullptr;
+    size_t cap = 0;
+};
+
 // Device tables for one ordered set of solves of one (precision, leaf).
 struct Plan {
     std::vector<unsigned long long> ids;
@@ -129,6 +145,8 @@ struct Plan {
     SolveDesc *solves = nullptr;
     SolveState *gather = nullptr;
     SolveState *gather_host = nullptr;  // pinned
+    size_t pin_cap = 0;
+    std::vector<char> image;            // host image of the tables (source of their upload)
     int nsolve = 0;
     unsigned long long last_use = 0;
     hipGraph_t graph = nullptr;         // one captured iteration of this set
@@ -156,6 +174,10 @@ struct spamm_ctx {
     std::vector<hipStream_t> xstream;
     std::vector<hipEvent_t> xdone;
     void *scratch = nullptr;              // this device's copy of the static scratch
+    // recycled memory of the solve engine, and the solves begun and not finished
+    std::vector<Block> free_arena, free_table, free_pin;
+    std::vector<spamm_solve *> live;
+    int64_t allocs = 0;                   // device and pinned allocations made so far
 };
 
 struct spamm_solve {
@@ -179,6 +201,51 @@ struct spamm_solve {
 };
 
 namespace {
+
+// ---- pooled memory of the solve engine -------------------------------------
+// Takes the smallest pooled block of at least `bytes` (for solve arenas at
+// most about twice that, so a small solve does not hold a large block);
+// allocates only when none fits.
+int pool_take(spamm_ctx *ctx, std::vector<Block> &pool, size_t bytes, bool pinned, Block *out) {
+    if (bytes == 0) bytes = 256;
+    const bool bounded = &pool == &ctx->free_arena;
+    auto best = pool.end();
+    for (auto it = pool.begin(); it != pool.end(); ++it)
+        if (it->cap >= bytes && (!bounded || it->cap <= 2 * bytes + (1u << 20)) &&
+            (best == pool.end() || it->cap < best->cap))
+            best = it;
+    if (best != pool.end()) {
+        *out = *best;
+        pool.erase(best);
+        return SPAMM_OK;
+    }
+    void *p = nullptr;
+    const hipError_t e = pinned ? hipHostMalloc(&p, bytes, hipHostMallocDefault) : hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPAMM_ENOMEM, "%s of %zu bytes failed: %s", pinned ? "hipHostMalloc" : "hipMalloc", bytes,
+                    hipGetErrorString(e));
+    }
+    ++ctx->allocs;
+    *out = Block{(char *)p, bytes};
+    return SPAMM_OK;
+}
+
+void pool_give(std::vector<Block> &pool, Block b) {
+    if (b.p) pool.push_back(b);
+}
+
+// Frees every block of a pool (context teardown, or before retrying an
+// allocation that ran out of memory); synchronises the device.
+void pool_drain(std::vector<Block> &pool, bool pinned) {
+    for (const Block &b : pool) {
+        if (pinned)
+            (void)hipHostFree(b.p);
+        else
+            (void)hipFree(b.p);
+    }
+    pool.clear();
+}
 
 // ---- measurement hooks -----------------------------------------------------
 enum { K_GEMM = 0, K_CULL = 1, K_PYR = 2, K_NKINDS = 3 };
@@ -220,6 +287,7 @@ int ensure(spamm_ctx *ctx, int slot, size_t bytes) {
         (void)hipGetLastError();
         return fail(SPAMM_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
+    ++ctx->allocs;
     ctx->buf[slot] = p;
     ctx->cap[slot] = bytes;
     return SPAMM_OK;
@@ -460,12 +528,15 @@ SolveDesc solve_desc(const spamm_solve *s) {
     return d;
 }
 
-void free_plan(Plan *p) {
+// Drops a plan; its device tables and pinned read-back buffer return to the
+// context's pools (every step synchronises before it returns, so no work on
+// them is pending).
+void free_plan(spamm_ctx *ctx, Plan *p) {
     if (!p) return;
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->mem) (void)hipFree(p->mem);
-    if (p->gather_host) (void)hipHostFree(p->gather_host);
+    pool_give(ctx->free_table, Block{p->mem, p->cap});
+    pool_give(ctx->free_pin, Block{(char *)p->gather_host, p->pin_cap});
     delete p;
 }
 
@@ -474,7 +545,7 @@ void forget_solve(spamm_ctx *ctx, unsigned long long id) {
     for (size_t i = 0; i < ctx->plans.size();) {
         Plan *p = ctx->plans[i];
         if (std::find(p->ids.begin(), p->ids.end(), id) != p->ids.end()) {
-            free_plan(p);
+            free_plan(ctx, p);
             ctx->plans.erase(ctx->plans.begin() + i);
         } else {
             ++i;
@@ -482,8 +553,84 @@ void forget_solve(spamm_ctx *ctx, unsigned long long id) {
     }
 }
 
-// Tables for an ordered group of solves sharing (precision, leaf).
-int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_t st, Plan **out) {
+bool same_group(const spamm_solve *a, const spamm_solve *b) {
+    return a->prec == b->prec && a->g.b == b->g.b && a->single == b->single;
+}
+
+// Device bytes of the tables of a plan over `group` (all of one group).
+size_t plan_bytes(const std::vector<spamm_solve *> &group);
+
+// Product and solve descriptors of the tables of a plan over `group`.
+struct PlanDescs {
+    bool single = false;
+    std::vector<ProdDesc> px, pyz, pt, py, pz;
+    std::vector<SolveDesc> sd;
+};
+
+PlanDescs plan_descs(const std::vector<spamm_solve *> &group) {
+    PlanDescs d;
+    d.single = group[0]->single != 0;
+    for (spamm_solve *s : group) {
+        d.px.push_back(x_product(s));
+        if (d.single) {
+            d.pt.push_back(transpose_desc(s));
+            d.py.push_back(single_y_product(s));
+            d.pz.push_back(single_z_product(s));
+        } else {
+            d.pyz.push_back(update_product(s, 0));
+            d.pyz.push_back(update_product(s, 1));
+        }
+        d.sd.push_back(solve_desc(s));
+    }
+    return d;
+}
+
+// Lays out (c.base null: sizes only) the tables of a plan in c.
+void plan_layout(Carve &c, const PlanDescs &d, Plan *p, std::vector<char> *image) {
+    const ProdTable tx = layout_table(c, d.px.data(), (int)d.px.size(), image);
+    ProdTable tt{}, ty{}, tz{}, tyz{};
+    if (d.single) {
+        tt = layout_table(c, d.pt.data(), (int)d.pt.size(), image);
+        ty = layout_table(c, d.py.data(), (int)d.py.size(), image);
+        tz = layout_table(c, d.pz.data(), (int)d.pz.size(), image);
+    } else {
+        tyz = layout_table(c, d.pyz.data(), (int)d.pyz.size(), image);
+    }
+    const size_t o_sd = c.off;
+    SolveDesc *solves = c.take<SolveDesc>(d.sd.size());
+    SolveState *gather = c.take<SolveState>(d.sd.size());
+    if (image) {
+        image->resize(c.off);
+        std::memcpy(image->data() + o_sd, d.sd.data(), d.sd.size() * sizeof(SolveDesc));
+    }
+    if (p) {
+        p->tx = tx;
+        p->tt = tt;
+        p->ty = ty;
+        p->tz = tz;
+        p->tyz = tyz;
+        p->solves = solves;
+        p->gather = gather;
+    }
+}
+
+size_t plan_bytes(const std::vector<spamm_solve *> &group) {
+    Carve sizing{nullptr, 0};
+    plan_layout(sizing, plan_descs(group), nullptr, nullptr);
+    return sizing.off;
+}
+
+// Tables for an ordered group of solves sharing (precision, leaf, channel).
+// Plans with last_use > keep_after are in use by the current step and are
+// never dropped (the step holds their pointers until it has synchronised).
+// A new plan replaces the cached plans of its group that the step does not
+// use (a group's set changes as solves join and leave), and the cache holds
+// at most 8 plans besides those of the current step.  The tables come from
+// the context's pool and are uploaded on `st` from a host image the plan
+// keeps, so building a plan neither allocates (once the pool is warm) nor
+// synchronises.
+int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_t st, unsigned long long keep_after,
+             Plan **out) {
     std::vector<unsigned long long> ids;
     for (spamm_solve *s : group) ids.push_back(s->id);
     for (Plan *p : ctx->plans)
@@ -492,75 +639,59 @@ int get_plan(spamm_ctx *ctx, const std::vector<spamm_solve *> &group, hipStream_
             *out = p;
             return SPAMM_OK;
         }
-    const bool single = group[0]->single != 0;
-    std::vector<ProdDesc> px, pyz, pt, py, pz;
-    std::vector<SolveDesc> sd;
-    for (spamm_solve *s : group) {
-        px.push_back(x_product(s));
-        if (single) {
-            pt.push_back(transpose_desc(s));
-            py.push_back(single_y_product(s));
-            pz.push_back(single_z_product(s));
-        } else {
-            pyz.push_back(update_product(s, 0));
-            pyz.push_back(update_product(s, 1));
-        }
-        sd.push_back(solve_desc(s));
-    }
-    Carve sizing{nullptr, 0};
-    layout_table(sizing, px.data(), (int)px.size(), nullptr);
-    if (single) {
-        layout_table(sizing, pt.data(), (int)pt.size(), nullptr);
-        layout_table(sizing, py.data(), (int)py.size(), nullptr);
-        layout_table(sizing, pz.data(), (int)pz.size(), nullptr);
-    } else {
-        layout_table(sizing, pyz.data(), (int)pyz.size(), nullptr);
-    }
-    sizing.take<SolveDesc>(sd.size());
-    sizing.take<SolveState>(sd.size());
+    const PlanDescs d = plan_descs(group);
     Plan *p = new Plan();
     p->ids = ids;
     p->prec = group[0]->prec;
     p->leaf = group[0]->g.b;
     p->nsolve = (int)group.size();
-    p->single = single;
+    p->single = d.single;
     p->damped = std::any_of(group.begin(), group.end(), [](const spamm_solve *s) { return s->damped != 0; });
-    p->cap = sizing.off;
-    hipError_t e = hipMalloc((void **)&p->mem, p->cap);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&p->gather_host, sizeof(SolveState) * group.size(), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        free_plan(p);
-        return fail(SPAMM_ENOMEM, "table allocation failed: %s", hipGetErrorString(e));
+    Block tb, pb;
+    int rc = pool_take(ctx, ctx->free_table, plan_bytes(group), false, &tb);
+    if (rc == SPAMM_OK) {
+        p->mem = tb.p;
+        p->cap = tb.cap;
+        rc = pool_take(ctx, ctx->free_pin, sizeof(SolveState) * group.size(), true, &pb);
     }
-    std::vector<char> image;
+    if (rc == SPAMM_OK) {
+        p->gather_host = (SolveState *)pb.p;
+        p->pin_cap = pb.cap;
+    }
+    if (rc != SPAMM_OK) {
+        const std::string keep = g_err;
+        free_plan(ctx, p);
+        g_err = keep;
+        return rc;
+    }
     Carve c{p->mem, 0};
-    p->tx = layout_table(c, px.data(), (int)px.size(), &image);
-    if (single) {
-        p->tt = layout_table(c, pt.data(), (int)pt.size(), &image);
-        p->ty = layout_table(c, py.data(), (int)py.size(), &image);
-        p->tz = layout_table(c, pz.data(), (int)pz.size(), &image);
-    } else {
-        p->tyz = layout_table(c, pyz.data(), (int)pyz.size(), &image);
-    }
-    const size_t o_sd = c.off;
-    p->solves = c.take<SolveDesc>(sd.size());
-    p->gather = c.take<SolveState>(sd.size());
-    image.resize(c.off);
-    std::memcpy(image.data() + o_sd, sd.data(), sd.size() * sizeof(SolveDesc));
-    hipError_t ce = hipMemcpyAsync(p->mem, image.data(), image.size(), hipMemcpyHostToDevice, st);
-    if (ce == hipSuccess) ce = hipStreamSynchronize(st);  // the staging image must outlive the copy
+    plan_layout(c, d, p, &p->image);
+    const hipError_t ce = hipMemcpyAsync(p->mem, p->image.data(), p->image.size(), hipMemcpyHostToDevice, st);
     if (ce != hipSuccess) {
-        free_plan(p);
+        free_plan(ctx, p);
         return fail(SPAMM_EHIP, "table upload failed: %s", hipGetErrorString(ce));
     }
     p->last_use = ++ctx->use_clock;
+    for (size_t i = 0; i < ctx->plans.size();) {
+        Plan *q = ctx->plans[i];
+        const bool stale = q->last_use <= keep_after && q->prec == p->prec && q->leaf == p->leaf &&
+                           q->single == p->single;
+        if (stale) {
+            free_plan(ctx, q);
+            ctx->plans.erase(ctx->plans.begin() + i);
+        } else {
+            ++i;
+        }
+    }
     if (ctx->plans.size() >= 8) {
-        auto lru = std::min_element(ctx->plans.begin(), ctx->plans.end(),
-                                    [](Plan *a, Plan *b) { return a->last_use < b->last_use; });
-        free_plan(*lru);
-        ctx->plans.erase(lru);
+        auto lru = ctx->plans.end();
+        for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it)
+            if ((*it)->last_use <= keep_after && (lru == ctx->plans.end() || (*it)->last_use < (*lru)->last_use))
+                lru = it;
+        if (lru != ctx->plans.end()) {
+            free_plan(ctx, *lru);
+            ctx->plans.erase(lru);
+        }
     }
     ctx->plans.push_back(p);
     *out = p;
@@ -697,7 +828,7 @@ int validate_ns(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, double t
     if (!(tol > 0.0)) return fail(SPAMM_EINVAL, "tol must be > 0");
     if (maxit < 0 || maxit > 100000) return fail(SPAMM_EINVAL, "maxit must be in [0, 100000]");
     if (!valid_prec(o.prec)) return fail(SPAMM_EINVAL, "unknown precision %d", o.prec);
-    if (o.prec == SPAMM_BF16X3 && o.leaf == 16) return fail(SPAMM_EINVAL, "BF16x3 leaves need leaf 32 or 64");
+    if (split_bf16(o.prec) && o.leaf == 16) return fail(SPAMM_EINVAL, "split-bf16 leaves need leaf 32 or 64");
     if (!(o.mu_rel >= 0.0) || std::isinf(o.mu_rel)) return fail(SPAMM_EINVAL, "mu_rel must be finite and >= 0");
     if (std::isnan(o.tau_s) || std::isinf(o.tau_s)) return fail(SPAMM_EINVAL, "tau_s must be finite");
     return SPAMM_OK;
@@ -749,7 +880,7 @@ int validate_multiply(spamm_ctx *ctx, const double *A, const double *B, const do
     if (!B || !C) return fail(SPAMM_EINVAL, "NULL matrix pointer");
     if (!(tau >= 0.0) || std::isinf(tau)) return fail(SPAMM_EINVAL, "tau must be finite and >= 0");
     if (!valid_prec(prec)) return fail(SPAMM_EINVAL, "unknown precision %d", prec);
-    if (prec == SPAMM_BF16X3 && leaf == 16) return fail(SPAMM_EINVAL, "BF16x3 leaves need leaf 32 or 64");
+    if (split_bf16(prec) && leaf == 16) return fail(SPAMM_EINVAL, "split-bf16 leaves need leaf 32 or 64");
     return SPAMM_OK;
 }
 
@@ -807,8 +938,16 @@ int spamm_destroy(spamm_ctx *ctx) {
     if (!ctx) return SPAMM_OK;
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipDeviceSynchronize());
-    for (Plan *p : ctx->plans) free_plan(p);
+    for (Plan *p : ctx->plans) free_plan(ctx, p);
     ctx->plans.clear();
+    for (spamm_solve *sv : ctx->live) {  // solves begun and never finished
+        pool_give(ctx->free_arena, Block{sv->mem, sv->bytes});
+        delete sv;
+    }
+    ctx->live.clear();
+    pool_drain(ctx->free_arena, false);
+    pool_drain(ctx->free_table, false);
+    pool_drain(ctx->free_pin, true);
     for (hipEvent_t e : ctx->pool) HIPCHK(hipEventDestroy(e));
     if (ctx->gstream) HIPCHK(hipStreamDestroy(ctx->gstream));
     for (hipStream_t x : ctx->xstream) HIPCHK(hipStreamDestroy(x));
@@ -1014,13 +1153,20 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
     sv->mem = nullptr;
     sv->single = o.single ? 1 : 0;
     sv->bytes = solve_bytes(g, o.prec, maxit, sv->single, nullptr);
-    hipError_t e = hipMalloc((void **)&sv->mem, sv->bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        delete sv;
-        return fail(SPAMM_ENOMEM, "solve allocation of %zu bytes failed: %s", (size_t)sv->bytes,
-                    hipGetErrorString(e));
+    Block arena;
+    int prc = pool_take(ctx, ctx->free_arena, sv->bytes, false, &arena);
+    if (prc == SPAMM_ENOMEM && !(ctx->free_arena.empty() && ctx->free_table.empty())) {
+        // memory held in the pools goes back to the device, then one retry
+        pool_drain(ctx->free_arena, false);
+        pool_drain(ctx->free_table, false);
+        prc = pool_take(ctx, ctx->free_arena, sv->bytes, false, &arena);
     }
+    if (prc != SPAMM_OK) {
+        delete sv;
+        return fail(SPAMM_ENOMEM, "solve allocation of %zu bytes failed", (size_t)sv->bytes);
+    }
+    sv->mem = arena.p;
+    sv->bytes = arena.cap;
     solve_bytes(g, o.prec, maxit, sv->single, sv);
     const int kp = kernel_prec(o.prec);
     const size_t leafq = (size_t)g.P * g.P * sizeof(double);
@@ -1042,10 +1188,32 @@ int spamm_solve_begin(spamm_ctx *ctx, const double *s, int64_t n, int64_t ld, do
     chk(hipMemcpyAsync(sv->state, &sv->host_state, sizeof(SolveState), hipMemcpyHostToDevice, st), "state");
     chk(hipStreamSynchronize(st), "synchronise");
     if (rc != SPAMM_OK) {
-        (void)hipFree(sv->mem);
+        pool_give(ctx->free_arena, Block{sv->mem, sv->bytes});
         delete sv;
         return rc;
     }
+    // Reserve in the pools the tables and read-back buffer of a plan over
+    // every unfinished solve of this group, so that the steps that follow
+    // take them from there rather than allocating.
+    std::vector<spamm_solve *> group;
+    for (spamm_solve *x : ctx->live)
+        if (same_group(x, sv)) group.push_back(x);
+    group.push_back(sv);
+    Block tb, pb;
+    rc = pool_take(ctx, ctx->free_table, plan_bytes(group), false, &tb);
+    if (rc == SPAMM_OK) {
+        pool_give(ctx->free_table, tb);
+        rc = pool_take(ctx, ctx->free_pin, sizeof(SolveState) * group.size(), true, &pb);
+        if (rc == SPAMM_OK) pool_give(ctx->free_pin, pb);
+    }
+    if (rc != SPAMM_OK) {
+        const std::string keep = g_err;
+        pool_give(ctx->free_arena, Block{sv->mem, sv->bytes});
+        delete sv;
+        g_err = keep;
+        return rc;
+    }
+    ctx->live.push_back(sv);
     *out = sv;
     return SPAMM_OK;
 }
@@ -1080,27 +1248,33 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
     if (count < 0 || (count > 0 && !solves)) return fail(SPAMM_EINVAL, "bad solve list");
     if (iterations < 1) return fail(SPAMM_EINVAL, "iterations must be >= 1");
     hipStream_t st = (hipStream_t)stream;
-    // running solves, grouped by (precision, leaf) in the caller's order
-    std::vector<std::vector<spamm_solve *>> groups;
+    // the listed solves grouped by (precision, leaf, channel) in the caller's
+    // order.  A group keeps its stopped solves (the kernels skip them), so
+    // its plan and captured graph stay the same while solves stop; groups
+    // with no running solve are left out.
+    std::vector<std::vector<spamm_solve *>> all;
     for (int i = 0; i < count; ++i) {
         spamm_solve *s = solves[i];
         if (!s || s->ctx != ctx) return fail(SPAMM_EINVAL, "solve %d is NULL or belongs to another context", i);
         for (int j = 0; j < i; ++j)
             if (solves[j] == s) return fail(SPAMM_EINVAL, "solve %d appears twice", i);
-        if (s->host_state.status != ST_RUNNING) continue;
-        auto it = std::find_if(groups.begin(), groups.end(), [&](const std::vector<spamm_solve *> &gr) {
-            return gr[0]->prec == s->prec && gr[0]->g.b == s->g.b && gr[0]->single == s->single;
-        });
-        if (it == groups.end())
-            groups.push_back({s});
+        auto it = std::find_if(all.begin(), all.end(),
+                               [&](const std::vector<spamm_solve *> &gr) { return same_group(gr[0], s); });
+        if (it == all.end())
+            all.push_back({s});
         else
             it->push_back(s);
     }
+    std::vector<std::vector<spamm_solve *>> groups;
+    for (auto &gr : all)
+        if (std::any_of(gr.begin(), gr.end(), [](const spamm_solve *s) { return s->host_state.status == ST_RUNNING; }))
+            groups.push_back(gr);
     if (groups.empty()) return 0;
     std::vector<Plan *> plans;
+    const unsigned long long step_start = ctx->use_clock;
     for (auto &gr : groups) {
         Plan *p = nullptr;
-        TRY(get_plan(ctx, gr, st, &p));
+        TRY(get_plan(ctx, gr, st, step_start, &p));
         plans.push_back(p);
     }
     const bool use_graphs = ctx->graphs && !ctx->prof;
@@ -1289,7 +1463,8 @@ int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *s, double *Y, double *Z, int
                           st));
     HIPCHK(hipStreamSynchronize(st));
     forget_solve(ctx, s->id);
-    HIPCHK(hipFree(s->mem));
+    ctx->live.erase(std::remove(ctx->live.begin(), ctx->live.end(), s), ctx->live.end());
+    pool_give(ctx->free_arena, Block{s->mem, s->bytes});
     delete s;
     if (status == SPAMM_EDIVERGED) return fail(SPAMM_EDIVERGED, "iteration diverged at k = %d (r = %g)", k, h.r);
     return status;
@@ -1345,6 +1520,8 @@ int spamm_profile_enable(spamm_ctx *ctx, int enable) {
     }
     return SPAMM_OK;
 }
+
+int64_t spamm_alloc_count(spamm_ctx *ctx) { return ctx ? ctx->allocs : -1; }
 
 int spamm_profile_reset(spamm_ctx *ctx) {
     if (!ctx) return fail(SPAMM_EINVAL, "NULL context");

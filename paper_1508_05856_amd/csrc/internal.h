@@ -25,7 +25,9 @@ int64_t pyr_len(int P);
 // Offset of the level of side S inside a pyramid whose leaf level has side P.
 int64_t level_off(int P, int S);
 
-enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
+// leaf products on the bf16 matrix cores (FP32 tiles split into bf16 pieces)
+inline bool is_bf16(int gprec) { return gprec == P_BF16X3 || gprec == P_BF16X6; }
 
 // Dispatch order of output tiles: Morton (Z) order of the nb x nb tile grid.
 void tile_order(int nb, int32_t *order /* nb*nb */);
@@ -89,12 +91,12 @@ struct ProdDesc {
 constexpr int NBUCKET = 64;          // longest-first buckets of the large-table work-list sort
 constexpr int PLAN_SMALL_MAX = 16384;  // tables up to this many tiles are sorted by one workgroup
 constexpr int PLAN_HIST_ITEMS = 4;     // items per thread and pass of the large-table sort
-// BF16x3 leaf products: consecutive jobs of the longest-first order run in
+// Split-bf16 leaf products: consecutive jobs of the longest-first order run in
 // groups of this many tiles on one XCD (workgroup w runs on XCD w mod 8), so
 // neighbouring tiles share that XCD's L2.
 constexpr int BF3_XCD_RUN = 64;
 
-// BF16x3 products of 64x64 leaves run one workgroup per quad of output tiles
+// Split-bf16 products of 64x64 leaves run one workgroup per quad of output tiles
 // (2i..2i+1, 2j..2j+1): the quad's workgroup stages each A_ik and B_kj once
 // for the tiles of the quad that retain k.  The quad kernel keeps the union of
 // the four retained lists in LDS, for at most QUAD_NB_MAX tiles per side.

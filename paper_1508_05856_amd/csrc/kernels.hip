@@ -881,7 +881,7 @@ bool front_small(const ProdTable &t, int leaf, int gprec) {
 
 hipError_t launch_front_small(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
     const int esz = gprec == P_F64 ? 8 : 4;
-    const int run = gprec == P_BF16X3 ? BF3_XCD_RUN : 1;
+    const int run = is_bf16(gprec) ? BF3_XCD_RUN : 1;
     hipLaunchKernelGGL(k_front_small, dim3(1), dim3(1024), (t.max_nb + 1) * sizeof(int), st, t.prods, t.tile_pre,
                        t.morton, t.nprod, t.max_nb, leaf, esz, run, t.jobs, t.work_count);
     return hipGetLastError();
@@ -890,7 +890,7 @@ hipError_t launch_front_small(const ProdTable &t, int leaf, int gprec, hipStream
 hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
     const int esz = gprec == P_F64 ? 8 : 4;
     const int quad = quad_tiles(gprec, leaf) ? 1 : 0;
-    const int run = gprec == P_BF16X3 ? (quad ? BF3_XCD_RUN / 4 : BF3_XCD_RUN) : 1;
+    const int run = is_bf16(gprec) ? (quad ? BF3_XCD_RUN / 4 : BF3_XCD_RUN) : 1;
     if (t.hist_blocks == 0) {
         hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), (t.max_nb + 1) * sizeof(int), st, t.prods, t.tile_pre,
                            t.morton, t.nprod, t.max_nb, quad, t.work, t.work_count);

@@ -1,6 +1,7 @@
-// Leaf products of SpAMM on the gfx950 matrix cores: FP64, FP32 and BF16x3
-// tiles, one workgroup per output tile of a job list (per quad of output
-// tiles for BF16x3 at b = 64), with the fused Newton-Schulz epilogue.  Kept apart from the other kernels so that counter
+// Leaf products of SpAMM on the gfx950 matrix cores: FP64, FP32 and split
+// bf16 (BF16x3, BF16x6) tiles, one workgroup per output tile of a job list
+// (per quad of output tiles for BF16x3 at b = 64), with the fused
+// Newton-Schulz epilogue.  Kept apart from the other kernels so that counter
 // profiles of these kernels can be matched to their source.
 #include <hip/hip_runtime.h>
 
@@ -248,15 +249,21 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm(const Job *_
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3 leaf products.  Operands stay FP32 in HBM (norms and the cull use
-// those stored values); while a stage is staged into LDS every element is
-// split into bf16 planes, x = hi + lo with hi = bf16(x) and lo = bf16(x - hi)
-// (round to nearest even, x - hi exact), and each 16x16x32 block product is
-// hi*hi + hi*lo + lo*hi on the bf16 matrix cores, accumulated in FP32.  The
-// dropped lo*lo term and the split residual are O(2^-16) of |a||b|.
-// A is staged row-major (k contiguous per row); B is staged transposed (k
-// contiguous per column), the k pairs being packed by the conversion itself,
-// so both MFMA operands are single 16-byte LDS reads.
+// Split-bf16 leaf products.  Operands stay FP32 in HBM (norms and the cull
+// use those stored values); while a stage is staged into LDS every element is
+// split into NP bf16 planes, each piece the round-to-nearest-even bf16 of
+// what the previous pieces leave (every difference is exact in FP32):
+//   NP = 2 (BF16x3): x = hi + lo; the block product is hi*hi + hi*lo + lo*hi.
+//     The dropped lo*lo term and the split residual are O(2^-16) of |a||b|.
+//   NP = 3 (BF16x6): x = hi + mid + lo, exact for every FP32 value (three
+//     pieces of 8 significant bits and a sign each cover its 24); the block
+//     product is the six terms down to 2^-16: lo*hi, hi*lo, mid*mid, mid*hi,
+//     hi*mid, hi*hi, smallest first.  The dropped mid*lo, lo*mid, lo*lo are
+//     O(2^-24) of |a||b|, below the FP32 accumulation itself.
+// Each 16x16x32 block product runs on the bf16 matrix cores, accumulated in
+// FP32.  A is staged row-major (k contiguous per row); B is staged
+// transposed (k contiguous per column), the k pairs being packed by the
+// conversion itself, so both MFMA operands are single 16-byte LDS reads.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -275,22 +282,46 @@ struct Bf3Cfg {
     static constexpr int B_UN = (KS / 2) * (B / 4) / NT;  // (k pair, 4 columns) units of B per thread
 };
 
-// hi/lo split of two FP32 values into packed bf16 pairs
-__device__ inline void split2(float x0, float x1, unsigned &hi, unsigned &lo) {
-    const f2 v = {x0, x1};
-    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
-    const f2 hv = {__builtin_bit_cast(float, hi << 16), __builtin_bit_cast(float, hi & 0xffff0000u)};
-    const f2 d = v - hv;
-    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(d, bf16x2));
+// Split of two FP32 values into NP packed bf16 pairs, p[0] the leading piece.
+template <int NP>
+__device__ inline void split_pair(float x0, float x1, unsigned (&p)[NP]) {
+    f2 v = {x0, x1};
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        p[q] = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+        if (q + 1 < NP) {
+            const f2 pv = {__builtin_bit_cast(float, p[q] << 16), __builtin_bit_cast(float, p[q] & 0xffff0000u)};
+            v = v - pv;
+        }
+    }
 }
 
-template <int B>
+// One 16x16x32 block product of split operands (pieces [0] leading), the
+// terms summed smallest first into acc.
+template <int NP>
+__device__ inline v4f mma_split(const bf16x8 *a, const bf16x8 *b, v4f acc) {
+    if constexpr (NP == 2) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+template <int B, int NP>
 __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Job *__restrict__ jobs,
                                                                         const int32_t *__restrict__ work_count) {
     using C = Bf3Cfg<B>;
-    // [buffer][plane hi/lo][rows x LDK]
-    __shared__ __attribute__((aligned(16))) __bf16 As[2][2][B * C::LDK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bt[2][2][B * C::LDK];
+    // [buffer][plane][rows x LDK]
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][NP][B * C::LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[2][NP][B * C::LDK];
     __shared__ double red[3 * C::WAVES];
 
     const int nwork = *work_count;
@@ -308,13 +339,26 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
     constexpr int64_t TS = (int64_t)B * B;
     const int S = cnt * C::SPT;
 
+    // NP = 2: one FP32 accumulator over the whole k list.  NP = 3: each
+    // stage's six terms are summed in FP32 from zero and the stage sums in
+    // FP64, so the FP32 rounding is that of one 32-k block product.
+    constexpr bool ACC64 = NP == 3;
     v4f acc[C::NBLK][C::NBLK];
+    double acc64[ACC64 ? C::NBLK : 1][ACC64 ? C::NBLK : 1][4];
 #pragma unroll
     for (int bi = 0; bi < C::NBLK; ++bi)
 #pragma unroll
         for (int bj = 0; bj < C::NBLK; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0.0f;
+    if constexpr (ACC64) {
+#pragma unroll
+        for (int bi = 0; bi < C::NBLK; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < C::NBLK; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc64[bi][bj][r] = 0.0;
+    }
 
     // stage s: k-columns [ks*KS, ks*KS+KS) of triple (i, j, list[s/SPT]).
     // A chunk c: 4 consecutive k of one row.  B unit u: rows 2kp and 2kp+1
@@ -343,12 +387,12 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
         for (int c = 0; c < C::A_CH; ++c) {
             const int el = (tid + c * C::NT) * 4;
             const int row = el / C::KS, k = el % C::KS;
-            unsigned h0, l0, h1, l1;
-            split2(ra[c][0], ra[c][1], h0, l0);
-            split2(ra[c][2], ra[c][3], h1, l1);
+            unsigned p0[NP], p1[NP];
+            split_pair<NP>(ra[c][0], ra[c][1], p0);
+            split_pair<NP>(ra[c][2], ra[c][3], p1);
             typedef unsigned u2 __attribute__((ext_vector_type(2)));
-            *(u2 *)&As[buf][0][row * C::LDK + k] = u2{h0, h1};
-            *(u2 *)&As[buf][1][row * C::LDK + k] = u2{l0, l1};
+#pragma unroll
+            for (int q = 0; q < NP; ++q) *(u2 *)&As[buf][q][row * C::LDK + k] = u2{p0[q], p1[q]};
         }
 #pragma unroll
         for (int c = 0; c < C::B_UN; ++c) {
@@ -356,38 +400,42 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
             const int kp = u % (C::KS / 2), cg = u / (C::KS / 2);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                unsigned h, l;
-                split2(rb[2 * c][q], rb[2 * c + 1][q], h, l);  // (k, k+1) of column 4cg+q
+                unsigned pp[NP];
+                split_pair<NP>(rb[2 * c][q], rb[2 * c + 1][q], pp);  // (k, k+1) of column 4cg+q
                 const int col = 4 * cg + q;
-                *(unsigned *)&Bt[buf][0][col * C::LDK + 2 * kp] = h;
-                *(unsigned *)&Bt[buf][1][col * C::LDK + 2 * kp] = l;
+#pragma unroll
+                for (int x = 0; x < NP; ++x) *(unsigned *)&Bt[buf][x][col * C::LDK + 2 * kp] = pp[x];
             }
         }
     };
     auto compute = [&](int buf) {
         // operand layout of the 16x16x32 bf16 MFMA: lane l supplies row (A) or
         // column (B) l%16 at k = 8(l/16) .. 8(l/16)+7
-        bf16x8 ah[C::NBLK], al[C::NBLK], bh[C::NBLK], bl[C::NBLK];
+        bf16x8 af[C::NBLK][NP], bf[C::NBLK][NP];
         const int ko = 8 * (lane >> 4);
 #pragma unroll
         for (int bi = 0; bi < C::NBLK; ++bi) {
             const int row = wr * C::Q + bi * 16 + (lane & 15);
-            ah[bi] = *(const bf16x8 *)&As[buf][0][row * C::LDK + ko];
-            al[bi] = *(const bf16x8 *)&As[buf][1][row * C::LDK + ko];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) af[bi][q] = *(const bf16x8 *)&As[buf][q][row * C::LDK + ko];
         }
 #pragma unroll
         for (int bj = 0; bj < C::NBLK; ++bj) {
             const int col = wc * C::Q + bj * 16 + (lane & 15);
-            bh[bj] = *(const bf16x8 *)&Bt[buf][0][col * C::LDK + ko];
-            bl[bj] = *(const bf16x8 *)&Bt[buf][1][col * C::LDK + ko];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) bf[bj][q] = *(const bf16x8 *)&Bt[buf][q][col * C::LDK + ko];
         }
 #pragma unroll
         for (int bi = 0; bi < C::NBLK; ++bi)
 #pragma unroll
             for (int bj = 0; bj < C::NBLK; ++bj) {
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+                if constexpr (ACC64) {
+                    const v4f t = mma_split<NP>(af[bi], bf[bj], v4f{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[bi][bj][r] += (double)t[r];
+                } else {
+                    acc[bi][bj] = mma_split<NP>(af[bi], bf[bj], acc[bi][bj]);
+                }
             }
     };
 
@@ -423,7 +471,11 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
             for (int r = 0; r < 4; ++r) {
                 const int row = wr * C::Q + bi * 16 + 4 * (lane >> 4) + r;
                 const int col = wc * C::Q + bj * 16 + (lane & 15);
-                const double x = (double)acc[bi][bj][r];
+                double x;
+                if constexpr (ACC64)
+                    x = acc64[bi][bj][r];
+                else
+                    x = (double)acc[bi][bj][r];
                 float out;
                 if (nsx) {
                     const int64_t gi = (int64_t)i * B + row, gj = (int64_t)j * B + col;
@@ -506,9 +558,10 @@ __global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restric
                                                            const int32_t *__restrict__ work_count) {
     using C = Bf3Quad;
     constexpr int B = C::B;
-    // [buffer][row half di / column half dj][plane hi/lo][...]
-    __shared__ __attribute__((aligned(16))) __bf16 As[2][2][2][B * C::LDA];
-    __shared__ __attribute__((aligned(16))) __bf16 Bt[2][2][2][B * C::LDB];
+    constexpr int NP = 2;  // BF16x3 pieces
+    // [buffer][row half di / column half dj][plane][...]
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][2][NP][B * C::LDA];
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[2][2][NP][B * C::LDB];
     __shared__ unsigned umask[QUAD_NB_MAX / 4];  // byte k%4 of word k/4: tiles retaining k
     __shared__ unsigned ulist[QUAD_NB_MAX];      // k | mask << 16, increasing k
     __shared__ int wtot[4];
@@ -606,22 +659,22 @@ __global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restric
                 for (int c = 0; c < C::A_CH; ++c) {
                     const int el = (tid + c * C::NT) * 4;
                     const int row = el / C::KS, k = el % C::KS;
-                    unsigned h0, l0, h1, l1;
-                    split2(r[2 * h + c][0], r[2 * h + c][1], h0, l0);
-                    split2(r[2 * h + c][2], r[2 * h + c][3], h1, l1);
-                    *(u2 *)&As[buf][h][0][swz_a(row, k)] = u2{h0, h1};
-                    *(u2 *)&As[buf][h][1][swz_a(row, k)] = u2{l0, l1};
+                    unsigned p0[NP], p1[NP];
+                    split_pair<NP>(r[2 * h + c][0], r[2 * h + c][1], p0);
+                    split_pair<NP>(r[2 * h + c][2], r[2 * h + c][3], p1);
+#pragma unroll
+                    for (int x = 0; x < NP; ++x) *(u2 *)&As[buf][h][x][swz_a(row, k)] = u2{p0[x], p1[x]};
                 }
             }
             if (needB(m, h)) {
                 const int kp = tid % (C::KS / 2), cg = tid / (C::KS / 2);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    unsigned hi, lo;
-                    split2(r[4 + 2 * h][q], r[5 + 2 * h][q], hi, lo);  // (k, k+1) of column 4cg+q
+                    unsigned pp[NP];
+                    split_pair<NP>(r[4 + 2 * h][q], r[5 + 2 * h][q], pp);  // (k, k+1) of column 4cg+q
                     const int col = 4 * cg + q;
-                    *(unsigned *)&Bt[buf][h][0][col * C::LDB + 2 * kp] = hi;
-                    *(unsigned *)&Bt[buf][h][1][col * C::LDB + 2 * kp] = lo;
+#pragma unroll
+                    for (int x = 0; x < NP; ++x) *(unsigned *)&Bt[buf][h][x][col * C::LDB + 2 * kp] = pp[x];
                 }
             }
         }
@@ -632,24 +685,21 @@ __global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restric
         // operand layout of the 16x16x32 bf16 MFMA: lane l supplies row (A) or
         // column (B) l%16 at k = 8(l/16) .. 8(l/16)+7
         const int ko = 8 * (lane >> 4);
-        bf16x8 ah[4], al[4];
+        bf16x8 af[4][NP];
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi) {
             const int row = bi * 16 + (lane & 15);
-            ah[bi] = *(const bf16x8 *)&As[buf][di][0][swz_a(row, ko)];
-            al[bi] = *(const bf16x8 *)&As[buf][di][1][swz_a(row, ko)];
+#pragma unroll
+            for (int x = 0; x < NP; ++x) af[bi][x] = *(const bf16x8 *)&As[buf][di][x][swz_a(row, ko)];
         }
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) {
             const int col = bj * 16 + (lane & 15);
-            const bf16x8 bh = *(const bf16x8 *)&Bt[buf][dj][0][col * C::LDB + ko];
-            const bf16x8 bl = *(const bf16x8 *)&Bt[buf][dj][1][col * C::LDB + ko];
+            bf16x8 bf[NP];
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) {
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bh, acc[bi][bj], 0, 0, 0);
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bl, acc[bi][bj], 0, 0, 0);
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bh, acc[bi][bj], 0, 0, 0);
-            }
+            for (int x = 0; x < NP; ++x) bf[x] = *(const bf16x8 *)&Bt[buf][dj][x][col * C::LDB + ko];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) acc[bi][bj] = mma_split<NP>(af[bi], bf, acc[bi][bj]);
         }
     };
 
@@ -748,7 +798,17 @@ hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t s
             hipLaunchKernelGGL(k_leaf_gemm_bf3_quad, dim3(t.total_quads), dim3(Bf3Quad::NT), 0, st, t.jobs,
                                t.work_count);
         else if (leaf == 32)
-            hipLaunchKernelGGL(k_leaf_gemm_bf3<32>, dim3(t.total_tiles), dim3(64), 0, st, t.jobs, t.work_count);
+            hipLaunchKernelGGL((k_leaf_gemm_bf3<32, 2>), dim3(t.total_tiles), dim3(64), 0, st, t.jobs,
+                               t.work_count);
+        else
+            return hipErrorInvalidValue;
+    } else if (prec == P_BF16X6) {
+        if (leaf == 64)
+            hipLaunchKernelGGL((k_leaf_gemm_bf3<64, 3>), dim3(t.total_tiles), dim3(256), 0, st, t.jobs,
+                               t.work_count);
+        else if (leaf == 32)
+            hipLaunchKernelGGL((k_leaf_gemm_bf3<32, 3>), dim3(t.total_tiles), dim3(64), 0, st, t.jobs,
+                               t.work_count);
         else
             return hipErrorInvalidValue;
     } else {

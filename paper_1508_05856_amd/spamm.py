@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libspamm.so")
 
 OK, NOT_CONVERGED, STAGNATED = 0, 1, 2
 EINVAL, ENOMEM, EDIVERGED, EHIP, ECAPACITY = -1, -2, -3, -4, -5
-F64, F32, BF16X3 = 0, 1, 2
-_PREC = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, "bf16x3": BF16X3}
+F64, F32, BF16X3, BF16X6 = 0, 1, 2, 3
+_PREC = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 
 STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", STAGNATED: "STAGNATED", EINVAL: "EINVAL",
                 ENOMEM: "ENOMEM", EDIVERGED: "EDIVERGED", EHIP: "EHIP", ECAPACITY: "ECAPACITY"}
@@ -29,7 +29,7 @@ EXPORTS = ("spamm_create", "spamm_destroy", "spamm_last_error", "spamm_pyramid_l
            "spamm_multiply", "ns_sqrt", "spamm_ns_history", "spamm_solve_footprint", "spamm_solve_begin",
            "spamm_solve_step", "spamm_solve_poll", "spamm_solve_finish", "spamm_set_graphs", "spamm_profile_enable",
            "spamm_profile_read", "spamm_profile_reset", "spamm_solve_triples", "spamm_product_rep",
-           "spamm_multiply_noalloc")
+           "spamm_multiply_noalloc", "spamm_alloc_count")
 MAX_SLICES = 16
 KIND_GEMM, KIND_CULL, KIND_PYRAMID = 0, 1, 2
 
@@ -111,6 +111,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.spamm_set_graphs.restype = ctypes.c_int
         lib.spamm_profile_reset.argtypes = [vp]
         lib.spamm_profile_read.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
+        lib.spamm_alloc_count.argtypes = [vp]
+        lib.spamm_alloc_count.restype = ctypes.c_int64
         for f in (lib.spamm_create, lib.spamm_destroy, lib.spamm_norms, lib.spamm_multiply, lib.ns_sqrt,
                   lib.spamm_ns_history, lib.spamm_profile_enable, lib.spamm_profile_reset,
                   lib.spamm_profile_read, lib.spamm_solve_begin, lib.spamm_solve_step, lib.spamm_solve_poll,
@@ -301,6 +303,10 @@ class Context:
 
     def profile(self, enable: bool = True):
         _check(self.lib.spamm_profile_enable(self.handle, int(bool(enable))))
+
+    def alloc_count(self) -> int:
+        """Device and pinned allocations this context has made so far."""
+        return int(self.lib.spamm_alloc_count(self.handle))
 
     def profile_reset(self):
         _check(self.lib.spamm_profile_reset(self.handle))

@@ -233,3 +233,65 @@ def test_graph_replays_equal_plain_launches(ctx):
         np.testing.assert_array_equal(ya, yb)
         np.testing.assert_array_equal(za, zb)
         np.testing.assert_array_equal(ya, yc)
+
+
+def test_step_with_more_groups_than_the_plan_cache(ctx):
+    """One step over solves of 12 distinct (precision, leaf, channel) groups,
+    more than the context caches plans for: every group's plan stays alive
+    until the step has synchronised, and each solve equals its solo run bit
+    for bit."""
+    groups = [(p, lf, sg) for p in ("f64", "f32", "bf16x3", "bf16x6") for lf in (32, 64) for sg in (False, True)
+              if not (p == "f32" and lf == 64)]
+    assert len(groups) == 14
+    mats = [inputs.kms(128 + 16 * i, 0.5 + 0.02 * i) for i in range(len(groups))]
+    solo_out = [ctx.ns_sqrt(dev(s), 1e-8, 1e-8, 12, leaf=lf, prec=p, single=sg, stagnation_stop=True)
+                for s, (p, lf, sg) in zip(mats, groups)]
+    solves = [ctx.solve_begin(dev(s), 1e-8, 1e-8, 12, leaf=lf, prec=p, single=sg, stagnation_stop=True)
+              for s, (p, lf, sg) in zip(mats, groups)]
+    while ctx.solve_step(solves, 3) > 0:
+        pass
+    for sv, (Ys, Zs, infos), g in zip(solves, solo_out, groups):
+        Y, Z, info = sv.finish()
+        assert info["iterations"] == infos["iterations"], g
+        assert torch.equal(Y, Ys) and torch.equal(Z, Zs), g
+
+
+def test_warm_context_steps_and_finishes_without_allocating():
+    """Solve memory and tables are pooled, not freed: once a set of solves has
+    run, the same set begun again allocates nothing, and on a warm context a
+    solve joining a running set (its begin reserves the group's tables) and
+    a solve leaving it are stepped and finished without any allocation."""
+    from paper_1508_05856_amd import spamm
+    c = spamm.Context(0)
+    try:
+        mats = [inputs.kms(300, 0.7), inputs.gauss_gramian(7, 1.0), inputs.kms(500, 0.6)]
+
+        def run_all():
+            a0 = c.alloc_count()
+            svs = [c.solve_begin(dev(m), 1e-8, 1e-9, 20, leaf=32, stagnation_stop=True) for m in mats]
+            a1 = c.alloc_count()
+            while c.solve_step(svs, 2) > 0:
+                pass
+            outs = [sv.finish() for sv in svs]
+            return a0, a1, c.alloc_count(), outs
+
+        _, _, _, first = run_all()
+        a0, a1, a2, second = run_all()
+        assert a2 == a1 == a0, (a0, a1, a2)
+        for (Y1, Z1, i1), (Y2, Z2, i2) in zip(first, second):
+            assert torch.equal(Y1, Y2) and torch.equal(Z1, Z2) and i1["iterations"] == i2["iterations"]
+        # join and leave on the warm context
+        A = c.solve_begin(dev(mats[0]), 1e-8, 1e-9, 20, leaf=32, stagnation_stop=True)
+        c.solve_step([A], 1)
+        B = c.solve_begin(dev(mats[2]), 1e-8, 1e-9, 20, leaf=32, stagnation_stop=True)
+        b0 = c.alloc_count()
+        c.solve_step([A, B], 1)
+        A.finish()  # leaves after two iterations
+        while c.solve_step([B], 2) > 0:
+            pass
+        YB, ZB, _ = B.finish()
+        assert c.alloc_count() == b0
+        # B joined a running solve and saw it leave: still bitwise its run with the others
+        assert torch.equal(YB, first[2][0]) and torch.equal(ZB, first[2][1])
+    finally:
+        c.close()

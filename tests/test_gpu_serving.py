@@ -139,3 +139,24 @@ def test_invalid_request_fails_alone(solo_results):
     for i, r in res.items():
         np.testing.assert_array_equal(r.Y.cpu().numpy(), solo_results[i][0])
         np.testing.assert_array_equal(r.Z.cpu().numpy(), solo_results[i][1])
+
+
+def test_served_results_match_the_fp64_oracle():
+    """Served results against the oracle itself, not only against solo runs:
+    small requests of each kind sharing the server, FP64 leaves, Y and Z to
+    1e-12 (relative Frobenius) with the oracle's status and update count."""
+    import oracle
+    from paper_1508_05856_amd import serve
+    picks = [REQS[0], REQS[3], REQS[5], REQS[1]]
+    srv = serve.Server(0, iters_per_step=2)
+    futs = [srv.submit(mat(kind, n, p, sd), tau, 1e-8, maxit=40, leaf=leaf, stagnation_stop=True)
+            for kind, n, p, sd, leaf, tau in picks]
+    results = [f.result(timeout=120) for f in futs]
+    srv.close()
+    for (kind, n, p, sd, leaf, tau), r in zip(picks, results):
+        s = inputs.build_spec(dict(kind=kind, n=n, seed=sd, rho=p, h=p))
+        o = oracle.ns_sqrt(s, leaf, tau, 1e-8, 40, stagnation_stop=True)
+        assert r.info["status"] == o["status"] and r.info["iterations"] == o["iterations"], (kind, n)
+        Y, Z = r.Y.cpu().numpy(), r.Z.cpu().numpy()
+        assert np.linalg.norm(Y - o["Y"]) <= 1e-12 * np.linalg.norm(o["Y"]), (kind, n)
+        assert np.linalg.norm(Z - o["Z"]) <= 1e-12 * np.linalg.norm(o["Z"]), (kind, n)
