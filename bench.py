@@ -1,16 +1,23 @@
 """Benchmark: Newton-Schulz square-root solves per second on one MI355X.
 
-One step = one complete ns_sqrt solve (ingest, norm pyramids, culls, leaf
-products with the fused update, convergence tests, egress) of the 3-D Gaussian
-overlap Gramian on 16^3 = 4096 Morton-ordered jittered lattice sites (h = 1.0,
-jitter 0.1, seed 0), leaf 64, FP64 leaves, with the input already resident in
-HBM.  Prints one JSON line.
+Default workload: the ill-conditioned Gaussian overlap Gramian on 32^3 = 32768
+Morton-ordered jittered lattice sites (h = 0.6, jitter 0.1, seed 0), shifted
+by mu = 1e-4 c0 (Sec. 6), leaf 64, tau = 1e-9 with the damped map and
+tau_s = 0.01 tau, stagnation stop, FP64 leaves (the paper's arithmetic), with
+the input already resident in HBM.  One step = one Newton-Schulz iteration of
+a stream of such solves (x product with its stop test, then the y and z
+update while the solve goes on); each solve is begun (ingest, pyramids) and
+finished (egress) inside the timed region.  value = solves/s of the first
+solve that runs whole inside the timed region.  Prints one JSON line.
 
 The leaf-product kernel is timed live with HIP events that the library records
-on its own stream around every leaf-product launch; its algorithmic rate is
-2 b^3 |R| per launch over the measured launch time.  The CPU baseline times the
-FP64 oracle on a bounded sample of the same solve (its first few updates) and
-scales by retained-triple volume.
+on its own stream around every leaf-product launch of the timed region; its
+algorithmic rate is 2 b^3 |R| per launch over the measured launch time.  The
+CPU baseline times the FP64 oracle on a bounded sample (the pyramid and a
+sample of output tiles of the first product) scaled by retained triples.
+
+--workload c2 is the n = 4096 Gaussian Gramian (whole-solve steps; its CPU
+baseline is the oracle's whole solve with its agreement with the GPU).
 """
 from __future__ import annotations
 
@@ -26,7 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+# bf16 products executed per useful product by the split-bf16 modes
+EXEC_PER_USEFUL = {"f64": 1.0, "f32": 1.0, "bf16x3": 3.0, "bf16x6": 6.0}
 LEAF_SRC = os.path.join(ROOT, "paper_1508_05856_amd", "csrc", "leaf_gemm.hip")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "leaf_gemm_f64_gauss_n4096_b64_tau1e-8_traffic.md")
 
@@ -57,30 +66,34 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--tau", type=float, default=None)
     p.add_argument("--tau-s", type=float, default=-1.0)
-    p.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3"])
+    p.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3", "bf16x6"])
     p.add_argument("--tol", type=float, default=None)
     p.add_argument("--maxit", type=int, default=40)
     p.add_argument("--literal-stop", action="store_true", help="disable the stagnation stop")
     p.add_argument("--stagnation", action="store_true", help="c1: use the stagnation stop (default: literal)")
     p.add_argument("--damped", action="store_true", help="the damped map (alpha(t), eps(t) of the trace error)")
-    p.add_argument("--cpu-sample-iters", type=int, default=8)
     p.add_argument("--m", type=int, default=32, help="c3: lattice side, n = m^3 (16: the n = 4096 analogue, "
                    "which the oracle solves whole for the CPU baseline)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--dump-launches", default=None, help="write per-launch (flops, ms) of the timed steps")
     p.add_argument("--compare-f64", action="store_true", help="also solve in FP64 and report the relative gap")
     p.add_argument("--copy-bytes", type=int, default=1 << 31, help="copy: bytes read (and written) per launch")
-    p.add_argument("--workload", default="gauss4096",
-                   choices=["gauss4096", "c1", "c3", "batched", "serving", "copy", "product", "norms"],
-                   help="gauss4096: the n=4096 Gaussian Gramian (default); batched: 64 uneven solves "
-                        "together; serving: a Poisson request stream through the continuous-batching server")
+    p.add_argument("--workload", default="c3",
+                   choices=["c3", "c2", "gauss4096", "c1", "batched", "serving", "copy", "product", "norms"],
+                   help="c3: the n=32768 ill-conditioned Gramian, steps of one iteration (default); "
+                        "c2 (= gauss4096): the n=4096 Gaussian Gramian, whole-solve steps; batched: 64 uneven "
+                        "solves together; serving: a Poisson request stream through the continuous-batching server")
     p.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     p.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     p.add_argument("--nmax", type=int, default=16384, help="serving: largest n (log-uniform from 512)")
     p.add_argument("--iters-per-step", type=int, default=4, help="batched: iterations per synchronisation")
+    p.add_argument("--no-one-at-a-time", action="store_true",
+                   help="serving: skip the one-request-at-a-time replay of the same stream")
     p.add_argument("--lanes", default="2048,8192", help="serving: comma-separated largest n of each engine lane "
                    "but the last (each lane has its own stream); empty = one lane")
     a = p.parse_args()
+    if a.workload == "gauss4096":
+        a.workload = "c2"
     a.tau_cli, a.tol_cli = a.tau, a.tol
     if a.tau is None:
         a.tau = 1e-8
@@ -103,8 +116,8 @@ def run_batched(args):
     # the workload leaves the y-channel threshold unstated: the paper's default
     # tau_s = 0.01 tau (with tau_s = tau, 8 of the 64 Gramians bifurcate)
     tsr = 0.01
-    table = autotune.load(prec, 1e-6)
-    leaves = [autotune.choose_leaf(table, sp["kind"], sp["n"]) for sp in specs]
+    tables = {tau: autotune.load(prec, tau) for tau in sorted({sp["tau"] for sp in specs})}
+    leaves = [autotune.choose_leaf(tables[sp["tau"]], sp["kind"], sp["n"]) for sp in specs]
     mats = [torch.from_numpy(inputs.build_spec(sp)).cuda() for sp in specs]
     outs = [(torch.empty_like(m), torch.empty_like(m)) for m in mats]
     ctx = spamm.Context(0)
@@ -189,32 +202,46 @@ def run_serving(args):
     """Poisson arrivals of sqrt / inverse-sqrt requests (n log-uniform in
     [512, nmax], KMS and Gaussian, tau in {1e-4, 1e-6, 1e-8}, tol 1e-8, FP64)
     submitted in real time to the continuous-batching server; latency is
-    arrival to result on the device."""
+    arrival to result on the device.  The same request stream is then served
+    one request at a time (ns_sqrt after ns_sqrt in arrival order, each
+    request's service time measured, first-come first-served from its
+    arrival), the plain path the server is compared with; results are bitwise
+    the same either way, so both run at the same accuracy."""
     import threading
 
     import torch
 
-    from paper_1508_05856_amd import inputs, serve
+    from paper_1508_05856_amd import inputs, serve, spamm
 
     reqs = inputs.serving_requests(args.rate, args.duration, seed=0, nmin=512, nmax=args.nmax)
     dev = torch.device("cuda:0")
     lanes = tuple(int(x) for x in args.lanes.split(",") if x) + (None,)
+    opts = dict(maxit=40, leaf=64, prec="f64", stagnation_stop=True)
     srv = serve.Server(0, iters_per_step=args.iters_per_step, lanes=lanes)
     # warm up kernels and tables on a tiny stream
     for f in [srv.submit(inputs.kms_device(n, 0.7, dev), 1e-6, 1e-8, leaf=64) for n in (512, 1024)]:
         f.result()
+    # exact ||I - Y Z||_F is computed after the run for a sample of the
+    # results (every 10th request of n <= 4096), whose outputs are kept
+    sample = {i for i, r in enumerate(reqs) if i % 10 == 0 and r["n"] <= 4096}
+    kept = {}
     futures = [None] * len(reqs)
     done = [0]
     t0 = time.perf_counter()
 
-    def on_done(f):
-        # keep the timing and status; drop Y, Z so finished outputs do not pile up in HBM
-        if f.exception() is None:
-            res = f.result()
-            res.Y = res.Z = None
-        done[0] += 1
-        if done[0] % 100 == 0 or done[0] == len(reqs):
-            print(f"served {done[0]}/{len(reqs)} at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    def make_cb(i):
+        def on_done(f):
+            # keep the timing and status; drop Y, Z so finished outputs do not pile up in HBM
+            if f.exception() is None:
+                res = f.result()
+                if i in sample:
+                    kept[i] = (res.Y, res.Z)
+                res.Y = res.Z = None
+            done[0] += 1
+            if done[0] % 100 == 0 or done[0] == len(reqs):
+                print(f"served {done[0]}/{len(reqs)} at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+        return on_done
 
     def client():
         # inputs are materialised on the device at arrival; when the queue of
@@ -231,9 +258,8 @@ def run_serving(args):
                     break
                 time.sleep(0.0005)
             s = inputs.build_spec_device(r, dev)
-            f = srv.submit(s, r["tau"], 1e-8, maxit=40, leaf=64, prec="f64", tau_s=0.01 * r["tau"],
-                           stagnation_stop=True)
-            f.add_done_callback(on_done)
+            f = srv.submit(s, r["tau"], 1e-8, tau_s=0.01 * r["tau"], **opts)
+            f.add_done_callback(make_cb(i))
             futures[i] = f
             del s
 
@@ -252,24 +278,71 @@ def run_serving(args):
         srv.close()
         raise err[0]
     results, failed = [], 0
-    for f, r in zip(futures, reqs):
+    for i, (f, r) in enumerate(zip(futures, reqs)):
         try:
-            results.append((f.result(timeout=600), r))
+            results.append((f.result(timeout=600), r, i))
         except Exception as e:
             failed += 1
             print(f"request n={r['n']} failed: {e}", file=sys.stderr, flush=True)
     t_end = time.perf_counter() - t0
     stats = dict(srv.stats)
     srv.close()
-    lat = np.array([res.t_done - (t0 + r["t"]) for res, r in results])
-    statuses = [res.info["status"] for res, _ in results]
-    # a request whose solve diverged is answered (with its status) but is not a solve
-    nvalid = sum(1 for st in statuses if st >= 0)
+    lat = np.array([res.t_done - (t0 + r["t"]) for res, r, _ in results])
+    statuses = [res.info["status"] for res, _, _ in results]
+    # counted: solves that ended at tol or at the floor of their tau (OK or
+    # STAGNATED); diverged and not-converged ones are answered but not counted
+    counted = [st in (spamm.OK, spamm.STAGNATED) for st in statuses]
+    nvalid = sum(counted)
     div_by = {}
-    for (res, r) in results:
+    for res, r, _ in results:
         if res.info["status"] < 0:
             key = f'{r["kind"]} tau={r["tau"]:g}'
             div_by[key] = div_by.get(key, 0) + 1
+    # accuracy of the counted solves: in-loop residual of all of them, exact
+    # ||I - Y Z||_F of the kept sample, per tau
+    ctx = spamm.Context(0)
+    exact = {}
+    for i, (Y, Z) in kept.items():
+        C, _, _ = ctx.spamm_multiply(Y, Z, 0.0, 64)
+        C.diagonal().sub_(1.0)
+        exact[i] = float(torch.linalg.norm(C))
+        del C
+    kept.clear()
+
+    def pct(v):
+        v = np.asarray(v, dtype=float)
+        return None if v.size == 0 else {q: float(np.percentile(v, int(q[1:]))) for q in ("p0", "p50", "p90", "p100")}
+
+    accuracy = {}
+    for tau in sorted({r["tau"] for r in reqs}):
+        rin = [res.info["resid"] for (res, r, _), ok in zip(results, counted) if ok and r["tau"] == tau]
+        rex = [exact[i] for (res, r, i), ok in zip(results, counted) if ok and r["tau"] == tau and i in exact]
+        accuracy[f"tau={tau:g}"] = {"counted": len(rin), "resid_inloop": pct(rin), "resid_exact_sample": pct(rex),
+                                    "exact_sample_size": len(rex),
+                                    "meeting_tol_1e-8": sum(1 for x in rin if x < 1e-8)}
+
+    # the same stream one request at a time: each request's service time,
+    # then first-come first-served from its arrival
+    one = None
+    if not args.no_one_at_a_time:
+        service = []
+        for r in reqs:
+            s = inputs.build_spec_device(r, dev)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            _, _, info = ctx.ns_sqrt(s, r["tau"], 1e-8, tau_s=0.01 * r["tau"], raise_on_error=False, **opts)
+            service.append(time.perf_counter() - ts)
+            del s
+        t_free, lat1 = 0.0, []
+        for r, sv in zip(reqs, service):
+            start = max(r["t"], t_free)
+            t_free = start + sv
+            lat1.append(t_free - r["t"])
+        one = {"solves_per_s": nvalid / t_free, "makespan_s": t_free, "busy_s": float(sum(service)),
+               "capacity_solves_per_s": nvalid / float(sum(service)),
+               "p50_latency_s": float(np.percentile(lat1, 50)), "p99_latency_s": float(np.percentile(lat1, 99)),
+               "mean_latency_s": float(np.mean(lat1))}
+    ctx.close()
     line = {
         "metric": "NS sqrt serving: solves/sec and p50/p99 latency under Poisson arrivals",
         "value": nvalid / t_end, "unit": "solves/s", "n_gpus": 1, "steps": len(results), "warmup": 2,
@@ -277,7 +350,8 @@ def run_serving(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {
             "workload": f"serving_poisson_{args.rate:g}rps_{args.duration:g}s_n512-{args.nmax}",
-            "requests": len(reqs), "failed": failed, "valid_solves": nvalid, "diverged_by": div_by,
+            "counted": "solves ending at tol or at their tau floor (status OK or STAGNATED)",
+            "requests": len(reqs), "failed": failed, "counted_solves": nvalid, "diverged_by": div_by,
             "answered_per_s": len(results) / t_end, "offered_rate": args.rate, "duration_s": args.duration,
             "makespan_s": t_end, "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
@@ -285,7 +359,10 @@ def run_serving(args):
             "lanes": [x if x is not None else "rest" for x in lanes],
             "sizes_n": [int(min(r["n"] for r in reqs)), int(max(r["n"] for r in reqs))],
             "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
-            "useful_tflops": sum(res.info["flops_total"] for res, _ in results) / t_end / 1e12,
+            "accuracy_of_counted": accuracy,
+            "one_at_a_time": one,
+            "speedup_vs_one_at_a_time": (one["makespan_s"] / t_end) if one else None,
+            "useful_tflops": sum(res.info["flops_total"] for res, _, _ in results) / t_end / 1e12,
             "engine": stats,
         },
     }
@@ -297,18 +374,23 @@ ORACLE_FULL_MAX_N = 8192  # device-built inputs up to this n: the oracle solves 
 
 def cpu_baseline_full(s, leaf, args, mu_rel, stag, info, Y, Z):
     """The oracle's whole solve of the same input and options (FP64 leaves
-    whatever the GPU precision), timed, with its agreement with the GPU
-    outputs beside it."""
+    whatever the GPU precision), timed (the median of up to three runs, as
+    many as fit in about a minute), with its agreement with the GPU outputs
+    beside it."""
     import oracle
     a = s.cpu().numpy()
-    tc = time.perf_counter()
-    ores = oracle.ns_sqrt(a, leaf, args.tau, args.tol, args.maxit, tau_s=args.tau_s, mu_rel=mu_rel,
-                          stagnation_stop=stag, damped=args.damped)
-    sec = time.perf_counter() - tc
+    secs = []
+    while len(secs) < 3 and sum(secs) < 40.0:
+        tc = time.perf_counter()
+        ores = oracle.ns_sqrt(a, leaf, args.tau, args.tol, args.maxit, tau_s=args.tau_s, mu_rel=mu_rel,
+                              stagnation_stop=stag, damped=args.damped)
+        secs.append(time.perf_counter() - tc)
+    sec = float(np.median(secs))
     Yh, Zh = Y.cpu().numpy(), Z.cpu().numpy()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / sec, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"the whole solve (n = {a.shape[0]}, FP64 leaves): {sec:.1f} s",
+            "sample": (f"the whole solve (n = {a.shape[0]}, FP64 leaves), median of {len(secs)} run(s): "
+                       f"{', '.join(f'{x:.1f}' for x in secs)} s"),
             "agreement": {"status": [info["status"], int(ores["status"])],
                           "iterations": [info["iterations"], int(ores["iterations"])],
                           "rel_Y": float(np.linalg.norm(Yh - ores["Y"]) / np.linalg.norm(ores["Y"])),
@@ -352,6 +434,137 @@ def cpu_baseline_sampled_tiles(s, mu_rel, leaf, tau, info):
                        f"set-up) scaled to the solve's {info['triples_total']} triples")}
 
 
+def run_c3(args):
+    """The n = m^3 ill-conditioned Gramian (default m = 32, n = 32768), one
+    step = one Newton-Schulz iteration of a stream of solves.  W warm-up
+    iterations run on a solve that is then dropped; the timed region then
+    begins a solve (ingest), steps it iteration by iteration, finishes it
+    (egress) when its stop test fires and begins the next, until exactly K
+    iterations have run.  Leaf-product launches of the timed region are timed
+    with HIP events on the library's stream (plain launches; at this size a
+    launch lasts milliseconds, so replaying graphs would change nothing)."""
+    import torch
+
+    from paper_1508_05856_amd import inputs, spamm
+
+    cfg = inputs.config_c3_spec(args.m)
+    n, leaf, mu_rel = cfg["n"], cfg["leaf"], cfg["mu_rel"]
+    tau = cfg["tau"] if args.tau_cli is None else args.tau
+    tol = cfg["tol"] if args.tol_cli is None else args.tol
+    tau_s = cfg["tau_s_rel"] * tau if args.tau_s < 0 else args.tau_s
+    stag = not args.literal_stop
+    damped = True
+    dev = torch.device("cuda:0")
+    s = inputs.gramian_device(inputs.gauss_positions(cfg["m"], cfg["h"], 0.1, 0, n), dev)
+    Y, Z = torch.empty_like(s), torch.empty_like(s)
+    ctx = spamm.Context(0)
+    opts = dict(leaf=leaf, prec=args.prec, tau_s=tau_s, mu_rel=mu_rel, stagnation_stop=stag, damped=damped)
+
+    def history_flops(it_from, it_to):
+        """Useful flops of the leaf-product launches of iterations
+        [it_from, it_to) of the solve just finished (x product, then the y and
+        z update unless the solve stopped at that iteration)."""
+        r, t, nR = ctx.ns_history()
+        kfin = len(nR) - 1
+        fl = 0.0
+        for it in range(it_from, min(it_to, kfin + 1)):
+            fl += 2.0 * leaf ** 3 * nR[it, 0]
+            if it < kfin:
+                fl += 2.0 * leaf ** 3 * (nR[it, 1] + nR[it, 2])
+        return fl
+
+    sv = ctx.solve_begin(s, tau, tol, args.maxit, **opts)
+    for _ in range(args.warmup):
+        if ctx.solve_step([sv], 1) == 0:
+            break
+    sv.finish(want_outputs=False)
+
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, flops, k, sv, its, tb = [], 0.0, 0, None, 0, 0.0
+    while k < args.steps:
+        if sv is None:
+            tb = time.perf_counter()
+            sv = ctx.solve_begin(s, tau, tol, args.maxit, **opts)
+            its = 0
+        running = ctx.solve_step([sv], 1)
+        k += 1
+        its += 1
+        if running == 0:
+            _, _, info = sv.finish(Y, Z)
+            done.append(dict(seconds=time.perf_counter() - tb, info=info))
+            flops += history_flops(0, its)
+            sv = None
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gemm_ms = ctx.profile_read(spamm.KIND_GEMM)
+    cull_ms = ctx.profile_read(spamm.KIND_CULL)
+    pyr_ms = ctx.profile_read(spamm.KIND_PYRAMID)
+    ctx.profile(False)
+    if sv is not None:  # the partial solve the region ended in: its launches were timed too
+        sv.finish(want_outputs=False)
+        flops += history_flops(0, its)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    if done:
+        info = done[0]["info"]
+        sec_per_solve = done[0]["seconds"]
+        how = "the first solve run whole inside the timed region, ingest to egress"
+    else:
+        info = None
+        sec_per_solve = None
+        how = None
+
+    useful = flops / (float(np.sum(gemm_ms)) * 1e-3) / 1e12
+    achieved = EXEC_PER_USEFUL[args.prec] * useful
+    peak = PEAK_TFLOPS[args.prec]
+    resid_exact = None
+    if info is not None:
+        C, _, _ = ctx.spamm_multiply(Y, Z, 0.0, leaf)
+        C.diagonal().sub_(1.0)
+        resid_exact = float(torch.linalg.norm(C))
+        del C
+    line = {
+        "metric": "NS sqrt solves/sec at stated ||I-YZ||_F (culled-leaf TFLOP/s vs MFMA peak in roofline)",
+        "value": (1.0 / sec_per_solve) if sec_per_solve else None,
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.prec, "data": "synthetic",
+        "config": {
+            "workload": cfg["name"] + ("" if args.prec == "f64" else f"_{args.prec}"), "n": n, "leaf": leaf,
+            "tau": tau, "tau_s": tau_s, "tol": tol, "maxit": args.maxit, "mu_rel": mu_rel,
+            "stop": "stagnation" if stag else "literal", "precision": args.prec, "map": "damped",
+            "step": "one Newton-Schulz iteration (x product and stop test, then the y and z update)",
+            "value_from": how,
+            "solves_completed_in_timed_region": len(done),
+            "status": spamm.STATUS_NAMES.get(info["status"], info["status"]) if info else None,
+            "iterations": info["iterations"] if info else None,
+            "resid_inloop": info["resid"] if info else None, "resid_exact": resid_exact,
+            "trace_err": info["trace_err"] if info else None,
+            "triples_per_solve": info["triples_total"] if info else None,
+            "flops_per_solve": info["flops_total"] if info else None,
+            "seconds_per_solve": sec_per_solve,
+        },
+        "roofline": {
+            "bound": "mfma", "kernel": _gemm_kernel(args.prec, leaf), "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": committed_traffic(cfg["name"], args.prec), "traffic_unit": "bytes per launch",
+            "useful_tflops": useful, "launches": int(len(gemm_ms)), "avg_launch_ms": float(np.mean(gemm_ms)),
+            "gemm_ms_in_region": float(np.sum(gemm_ms)), "cull_ms_in_region": float(np.sum(cull_ms)),
+            "pyramid_ms_in_region": float(np.sum(pyr_ms)), "region_ms": (t1 - t0) * 1e3,
+            "timing": "HIP events on the library's stream around every leaf-product launch of the timed region",
+        },
+    }
+    if not args.no_cpu_baseline and info is not None:
+        if n <= ORACLE_FULL_MAX_N:
+            args.tau, args.tol, args.tau_s, args.damped = tau, tol, tau_s, damped
+            line["cpu_baseline"] = cpu_baseline_full(s, leaf, args, mu_rel, stag, info, Y, Z)
+        else:
+            line["cpu_baseline"] = cpu_baseline_sampled_tiles(s, mu_rel, leaf, tau, info)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def run_product(args):
     """One SpAMM product alone: y (x)_tau z of the n = 4096 Gaussian solve at
     its tau floor (the operands of its last x product, from an untimed FP64
@@ -379,10 +592,8 @@ def run_product(args):
     dt = (time.perf_counter() - t0) / args.steps
     g = ctx.profile_read(spamm.KIND_GEMM)
     ctx.profile(False)
-    achieved = st["flops"] / (float(np.mean(g)) * 1e-3) / 1e12
+    achieved = EXEC_PER_USEFUL[args.prec] * st["flops"] / (float(np.mean(g)) * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
-    if args.prec == "bf16x3":
-        achieved *= 3.0
     print(json.dumps({"metric": "SpAMM product y (x)_tau z at the n=4096 Gaussian solve's tau floor",
                       "value": st["flops"] / dt / 1e12, "unit": "useful TFLOP/s (whole product)", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
@@ -401,6 +612,8 @@ def _gemm_kernel(prec, leaf):
     """Name of the leaf-product kernel a precision and leaf size run."""
     if prec == "bf16x3":
         return "k_leaf_gemm_bf3_quad" if leaf == 64 else "k_leaf_gemm_bf3"
+    if prec == "bf16x6":
+        return "k_leaf_gemm_bf3"
     return "k_leaf_gemm"
 
 
@@ -486,6 +699,9 @@ def main():
     if args.workload == "norms":
         run_norms(args)
         return
+    if args.workload == "c3":
+        run_c3(args)
+        return
 
     import torch
 
@@ -494,21 +710,7 @@ def main():
     dev = torch.device("cuda:0")
     stag = not args.literal_stop
     mu_rel = 0.0
-    if args.workload == "c3":
-        # n = 32768 ill-conditioned Gramian, built on the device (8 GiB in FP64)
-        cfg = inputs.config_c3_spec(args.m)
-        n, leaf = cfg["n"], cfg["leaf"]
-        s_host = None
-        s = inputs.gramian_device(inputs.gauss_positions(cfg["m"], cfg["h"], 0.1, 0, n), dev)
-        mu_rel = cfg["mu_rel"]
-        if args.tau_cli is None:
-            args.tau = cfg["tau"]
-        if args.tol_cli is None:
-            args.tol = cfg["tol"]
-        if args.tau_s < 0:
-            args.tau_s = cfg["tau_s_rel"] * args.tau
-        args.damped = args.damped or cfg["damped"]
-    elif args.workload == "c1":
+    if args.workload == "c1":
         # KMS rho = 0.7, n = 512, leaf 32, stop at tol 1e-10 or 40 updates (the
         # literal rule unless --stagnation is given): launch-latency bound
         cfg = inputs.config_c1()
@@ -602,9 +804,10 @@ def main():
         with open(args.dump_launches, "w") as f:
             json.dump(dict(gemm_ms=gemm_ms, gemm_flops=gemm_flops, cull_ms=cull_ms, pyramid_ms=pyr_ms), f)
     useful = sum(gemm_flops) / (sum(gemm_ms) * 1e-3) / 1e12
-    # BF16x3 executes three bf16 products per useful one: its roofline is the
-    # executed rate against the bf16 peak (the useful rate is reported beside it)
-    achieved = 3.0 * useful if args.prec == "bf16x3" else useful
+    # the split-bf16 modes execute three or six bf16 products per useful one:
+    # their roofline is the executed rate against the bf16 peak (the useful
+    # rate is reported beside it)
+    achieved = EXEC_PER_USEFUL[args.prec] * useful
     peak = PEAK_TFLOPS[args.prec]
     line = {
         "metric": "NS sqrt solves/sec at stated ||I-YZ||_F (culled-leaf TFLOP/s vs MFMA peak in roofline)",
@@ -644,24 +847,27 @@ def main():
         },
     }
 
-    if not args.no_cpu_baseline and s_host is None and n <= ORACLE_FULL_MAX_N:
+    # the same workload under the other stop rule (the literal rule of tol or
+    # maxit beside the stagnation stop, or the reverse), timed over 3 solves
+    stag_other = not stag
+    Yo, Zo = torch.empty_like(s), torch.empty_like(s)
+    torch.cuda.synchronize()
+    to0 = time.perf_counter()
+    for _ in range(3):
+        _, _, oinfo = ctx.ns_sqrt(s, args.tau, args.tol, args.maxit, leaf=leaf, prec=args.prec, tau_s=args.tau_s,
+                                  mu_rel=mu_rel, stagnation_stop=stag_other, damped=args.damped, Y=Yo, Z=Zo,
+                                  raise_on_error=False)
+    torch.cuda.synchronize()
+    line["config"]["other_stop"] = {
+        "stop": "stagnation" if stag_other else "literal", "solves_per_s": 3.0 / (time.perf_counter() - to0),
+        "status": spamm.STATUS_NAMES.get(oinfo["status"], oinfo["status"]), "iterations": oinfo["iterations"],
+        "resid_inloop": oinfo["resid"]}
+    del Yo, Zo
+
+    if not args.no_cpu_baseline and n <= ORACLE_FULL_MAX_N:
         line["cpu_baseline"] = cpu_baseline_full(s, leaf, args, mu_rel, stag, info, Y, Z)
-    elif not args.no_cpu_baseline and s_host is None:
-        line["cpu_baseline"] = cpu_baseline_sampled_tiles(s, mu_rel, leaf, args.tau, info)
     elif not args.no_cpu_baseline:
-        import oracle
-        m = args.cpu_sample_iters
-        tc = time.perf_counter()
-        ores = oracle.ns_sqrt(s_host, leaf, args.tau, args.tol, m, tau_s=args.tau_s, stagnation_stop=stag)
-        tcpu = time.perf_counter() - tc
-        sample_triples = int(ores["nR"].sum())
-        sec_per_solve = tcpu * info["triples_total"] / max(sample_triples, 1)
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        line["cpu_baseline"] = {
-            "value": 1.0 / sec_per_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": (f"first {m} updates ({sample_triples} retained leaf triples) of the same solve took "
-                       f"{tcpu:.1f} s; scaled to the full solve's {info['triples_total']} triples"),
-        }
+        line["cpu_baseline"] = cpu_baseline_sampled_tiles(s, mu_rel, leaf, args.tau, info)
     ctx.close()
     print(json.dumps(line), flush=True)
 
