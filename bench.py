@@ -36,27 +36,32 @@ if ROOT not in sys.path:
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
 # bf16 products executed per useful product by the split-bf16 modes
 EXEC_PER_USEFUL = {"f64": 1.0, "f32": 1.0, "bf16x3": 3.0, "bf16x6": 6.0}
-LEAF_SRC = os.path.join(ROOT, "paper_1508_05856_amd", "csrc", "leaf_gemm.hip")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "leaf_gemm_f64_gauss_n4096_b64_tau1e-8_traffic.md")
+CSRC = os.path.join(ROOT, "paper_1508_05856_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def committed_traffic(workload: str, prec: str):
     """HBM bytes per leaf-product launch (FETCH_SIZE + WRITE_SIZE, each
-    scaled by the same counter on a plain copy of known size) from the
-    committed counter profile of this workload, or None when there is none
-    or the leaf-product source has changed since it was taken."""
+    scaled by the same counter on a plain copy of known size) from a committed
+    counter profile of this workload and precision, or None when there is
+    none or the leaf-product or job-order source (leaf_gemm.hip, kernels.hip)
+    has changed since it was taken."""
+    import glob
     import hashlib
     import re
-    if not os.path.exists(TRAFFIC_PROFILE):
-        return None
-    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_PROFILE).read(), re.S)
-    if not m:
-        return None
-    rec = json.loads(m.group(1))
-    sha = hashlib.sha256(open(LEAF_SRC, "rb").read()).hexdigest()
-    if rec.get("leaf_gemm_sha256") != sha or rec.get("workload") != workload or rec.get("prec") != prec:
-        return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    sha = {name: hashlib.sha256(open(os.path.join(CSRC, name), "rb").read()).hexdigest()
+           for name in ("leaf_gemm.hip", "kernels.hip")}
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*.md"))):
+        for block in re.findall(r"```json\n(.*?)\n```", open(path).read(), re.S):
+            try:
+                rec = json.loads(block)
+            except ValueError:
+                continue
+            if (rec.get("workload") == workload and rec.get("prec") == prec
+                    and rec.get("leaf_gemm_sha256") == sha["leaf_gemm.hip"]
+                    and rec.get("kernels_sha256") == sha["kernels.hip"]):
+                return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
 
 
 def parse():
@@ -87,6 +92,8 @@ def parse():
     p.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     p.add_argument("--nmax", type=int, default=16384, help="serving: largest n (log-uniform from 512)")
     p.add_argument("--iters-per-step", type=int, default=4, help="batched: iterations per synchronisation")
+    p.add_argument("--pool-share", type=float, default=0.2,
+                   help="serving: fraction of the admission budget each lane may keep pooled")
     p.add_argument("--no-one-at-a-time", action="store_true",
                    help="serving: skip the one-request-at-a-time replay of the same stream")
     p.add_argument("--lanes", default="2048,8192", help="serving: comma-separated largest n of each engine lane "
@@ -217,7 +224,7 @@ def run_serving(args):
     dev = torch.device("cuda:0")
     lanes = tuple(int(x) for x in args.lanes.split(",") if x) + (None,)
     opts = dict(maxit=40, leaf=64, prec="f64", stagnation_stop=True)
-    srv = serve.Server(0, iters_per_step=args.iters_per_step, lanes=lanes)
+    srv = serve.Server(0, iters_per_step=args.iters_per_step, lanes=lanes, pool_share=args.pool_share)
     # warm up kernels and tables on a tiny stream
     for f in [srv.submit(inputs.kms_device(n, 0.7, dev), 1e-6, 1e-8, leaf=64) for n in (512, 1024)]:
         f.result()

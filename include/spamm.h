@@ -221,7 +221,8 @@ typedef struct spamm_solve spamm_solve;
 size_t spamm_solve_footprint(int64_t n, int leaf, int prec, int maxit, int single);
 
 /* Checks s (as ns_sqrt), scales it, takes the solve's device memory from the
- * context's pool (allocating only when no pooled block fits) and sets
+ * context's pool (a block of at most 1.25 times the footprint plus 16 MiB;
+ * allocating only when no pooled block fits) and sets
  * y_0 = s', z_0 = I_n.  It also reserves in the pool the tables and pinned
  * read-back buffer of a step over every unfinished solve of its (precision,
  * leaf, channel) group on this context, so steps and finishes need no
@@ -311,10 +312,12 @@ int spamm_product_rep(spamm_ctx *ctx, const double *s, double *W, int64_t n, int
 int spamm_ns_history(spamm_ctx *ctx, double *r, double *t, int64_t *nR, int cap);
 
 /* Whether spamm_solve_step (and so ns_sqrt) replays each solve set's
- * iteration as a captured HIP graph (default 1).  The graph is captured on a
- * stream the context owns, ordered after the caller's stream by an event, and
- * the caller's stream is ordered after it; steps block the host either way.
- * While launch timing is enabled, plain launches are used. */
+ * iteration as a captured HIP graph (default 1).  The graph is captured on the
+ * set's second step (its first step launches plainly, so sets that last one
+ * step cost no capture), on a stream the context owns, ordered after the
+ * caller's stream by an event, and the caller's stream is ordered after it;
+ * steps block the host either way.  While launch timing is enabled, plain
+ * launches are used. */
 int spamm_set_graphs(spamm_ctx *ctx, int enable);
 
 /* Launch timing, for measurement.  While enabled, every leaf-product launch
@@ -343,6 +346,14 @@ int spamm_profile_reset(spamm_ctx *ctx);
  * warm context steps and finishes solves without adding to this count.
  * Returns -1 for a NULL context. */
 int64_t spamm_alloc_count(spamm_ctx *ctx);
+
+/* Largest number of device bytes the context keeps pooled (free solve arenas
+ * and plan tables; default: no limit).  Memory that a finishing solve or a
+ * dropped plan returns beyond it is freed at once, which synchronises the
+ * device; memory pooled beyond a new limit is freed now.  For callers that
+ * share the device with other allocations (a server sizing its admission
+ * budget).  Errors: EINVAL (NULL ctx), EHIP. */
+int spamm_set_pool_limit(spamm_ctx *ctx, size_t bytes);
 
 #ifdef __cplusplus
 }

@@ -147,6 +147,7 @@ struct Plan {
     SolveState *gather_host = nullptr;  // pinned
     size_t pin_cap = 0;
     std::vector<char> image;            // host image of the tables (source of their upload)
+    int uses = 0;                       // steps that have run this plan
     int nsolve = 0;
     unsigned long long last_use = 0;
     hipGraph_t graph = nullptr;         // one captured iteration of this set
@@ -178,6 +179,7 @@ struct spamm_ctx {
     std::vector<Block> free_arena, free_table, free_pin;
     std::vector<spamm_solve *> live;
     int64_t allocs = 0;                   // device and pinned allocations made so far
+    size_t pool_limit = SIZE_MAX;         // device bytes kept in free_arena + free_table at most
 };
 
 struct spamm_solve {
@@ -204,14 +206,14 @@ namespace {
 
 // ---- pooled memory of the solve engine -------------------------------------
 // Takes the smallest pooled block of at least `bytes` (for solve arenas at
-// most about twice that, so a small solve does not hold a large block);
-// allocates only when none fits.
+// most a quarter more, so a solve holds about its footprint); allocates only
+// when none fits.
 int pool_take(spamm_ctx *ctx, std::vector<Block> &pool, size_t bytes, bool pinned, Block *out) {
     if (bytes == 0) bytes = 256;
     const bool bounded = &pool == &ctx->free_arena;
     auto best = pool.end();
     for (auto it = pool.begin(); it != pool.end(); ++it)
-        if (it->cap >= bytes && (!bounded || it->cap <= 2 * bytes + (1u << 20)) &&
+        if (it->cap >= bytes && (!bounded || it->cap <= bytes + bytes / 4 + (16u << 20)) &&
             (best == pool.end() || it->cap < best->cap))
             best = it;
     if (best != pool.end()) {
@@ -231,8 +233,45 @@ int pool_take(spamm_ctx *ctx, std::vector<Block> &pool, size_t bytes, bool pinne
     return SPAMM_OK;
 }
 
+size_t pooled_device_bytes(const spamm_ctx *ctx) {
+    size_t t = 0;
+    for (const Block &b : ctx->free_arena) t += b.cap;
+    for (const Block &b : ctx->free_table) t += b.cap;
+    return t;
+}
+
 void pool_give(std::vector<Block> &pool, Block b) {
     if (b.p) pool.push_back(b);
+}
+
+// Device memory returned by a finished solve or a dropped plan: pooled, or
+// freed when pooling it would exceed the context's limit (hipFree then
+// synchronises the device).
+void pool_return(spamm_ctx *ctx, std::vector<Block> &pool, Block b) {
+    if (!b.p) return;
+    if (pooled_device_bytes(ctx) + b.cap > ctx->pool_limit) {
+        (void)hipFree(b.p);
+        return;
+    }
+    pool.push_back(b);
+}
+
+// Frees pooled device blocks, largest first, until at most `limit` bytes stay.
+void pool_trim(spamm_ctx *ctx, size_t limit) {
+    while (pooled_device_bytes(ctx) > limit) {
+        std::vector<Block> *from = nullptr;
+        size_t at = 0, best = 0;
+        for (std::vector<Block> *pl : {&ctx->free_arena, &ctx->free_table})
+            for (size_t i = 0; i < pl->size(); ++i)
+                if ((*pl)[i].cap >= best) {
+                    best = (*pl)[i].cap;
+                    from = pl;
+                    at = i;
+                }
+        if (!from) return;
+        (void)hipFree((*from)[at].p);
+        from->erase(from->begin() + at);
+    }
 }
 
 // Frees every block of a pool (context teardown, or before retrying an
@@ -535,7 +574,7 @@ void free_plan(spamm_ctx *ctx, Plan *p) {
     if (!p) return;
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    pool_give(ctx->free_table, Block{p->mem, p->cap});
+    pool_return(ctx, ctx->free_table, Block{p->mem, p->cap});
     pool_give(ctx->free_pin, Block{(char *)p->gather_host, p->pin_cap});
     delete p;
 }
@@ -1282,15 +1321,22 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
         // Plan q replays on its own stream (the graph stream for the first):
         // the plans touch disjoint solves, so they run concurrently.  Every
         // replay stream waits for the caller's stream, and the caller's stream
-        // waits for all of them (the step also blocks the host).
+        // waits for all of them (the step also blocks the host).  A plan's
+        // iteration is captured on the plan's second step: its first step
+        // launches plainly, so a set of solves that lasts one step (a server
+        // whose solves join and leave at every step boundary) never pays
+        // for a capture.
         for (Plan *p : plans)
-            if (!p->graph_exec) TRY(capture_iteration(ctx, p));
+            if (!p->graph_exec && p->uses > 0) TRY(capture_iteration(ctx, p));
         TRY(replay_streams(ctx, plans.size()));
         HIPCHK(hipEventRecord(ctx->ev_in, st));
         for (size_t q = 0; q < plans.size(); ++q) {
             hipStream_t rq = q == 0 ? ctx->gstream : ctx->xstream[q - 1];
             HIPCHK(hipStreamWaitEvent(rq, ctx->ev_in, 0));
-            for (int it = 0; it < iterations; ++it) HIPCHK(hipGraphLaunch(plans[q]->graph_exec, rq));
+            if (plans[q]->graph_exec)
+                for (int it = 0; it < iterations; ++it) HIPCHK(hipGraphLaunch(plans[q]->graph_exec, rq));
+            else
+                for (int it = 0; it < iterations; ++it) TRY(enqueue_iteration(ctx, plans[q], rq));
             HIPCHK(launch_gather_states(plans[q]->solves, plans[q]->nsolve, plans[q]->gather, rq));
             HIPCHK(hipMemcpyAsync(plans[q]->gather_host, plans[q]->gather, plans[q]->nsolve * sizeof(SolveState),
                                   hipMemcpyDeviceToHost, rq));
@@ -1310,6 +1356,7 @@ int spamm_solve_step(spamm_ctx *ctx, spamm_solve *const *solves, int count, int 
         }
         HIPCHK(hipStreamSynchronize(st));
     }
+    for (Plan *p : plans) ++p->uses;
     int running = 0;
     for (size_t gi = 0; gi < groups.size(); ++gi)
         for (size_t i = 0; i < groups[gi].size(); ++i) {
@@ -1464,7 +1511,7 @@ int spamm_solve_finish(spamm_ctx *ctx, spamm_solve *s, double *Y, double *Z, int
     HIPCHK(hipStreamSynchronize(st));
     forget_solve(ctx, s->id);
     ctx->live.erase(std::remove(ctx->live.begin(), ctx->live.end(), s), ctx->live.end());
-    pool_give(ctx->free_arena, Block{s->mem, s->bytes});
+    pool_return(ctx, ctx->free_arena, Block{s->mem, s->bytes});
     delete s;
     if (status == SPAMM_EDIVERGED) return fail(SPAMM_EDIVERGED, "iteration diverged at k = %d (r = %g)", k, h.r);
     return status;
@@ -1522,6 +1569,13 @@ int spamm_profile_enable(spamm_ctx *ctx, int enable) {
 }
 
 int64_t spamm_alloc_count(spamm_ctx *ctx) { return ctx ? ctx->allocs : -1; }
+
+int spamm_set_pool_limit(spamm_ctx *ctx, size_t bytes) {
+    TRY(enter(ctx));
+    ctx->pool_limit = bytes;
+    pool_trim(ctx, bytes);
+    return SPAMM_OK;
+}
 
 int spamm_profile_reset(spamm_ctx *ctx) {
     if (!ctx) return fail(SPAMM_EINVAL, "NULL context");

@@ -890,7 +890,11 @@ hipError_t launch_front_small(const ProdTable &t, int leaf, int gprec, hipStream
 hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
     const int esz = gprec == P_F64 ? 8 : 4;
     const int quad = quad_tiles(gprec, leaf) ? 1 : 0;
-    const int run = is_bf16(gprec) ? (quad ? BF3_XCD_RUN / 4 : BF3_XCD_RUN) : 1;
+    // FP64 products of large tables (beyond one-workgroup sorting) also run
+    // in XCD runs: their operands stream from HBM, and neighbouring tiles of
+    // a run share A rows and B columns in one L2
+    const int run = is_bf16(gprec) ? (quad ? BF3_XCD_RUN / 4 : BF3_XCD_RUN)
+                                   : (gprec == P_F64 && t.total_tiles > PLAN_SMALL_MAX ? BF3_XCD_RUN : 1);
     if (t.hist_blocks == 0) {
         hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), (t.max_nb + 1) * sizeof(int), st, t.prods, t.tile_pre,
                            t.morton, t.nprod, t.max_nb, quad, t.work, t.work_count);

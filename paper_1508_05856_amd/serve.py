@@ -69,9 +69,12 @@ class _Lane:
 
 class Server:
     def __init__(self, device: int = 0, hbm_budget: int | None = None, iters_per_step: int = 2,
-                 max_active: int = 512, autostart: bool = True, lanes: tuple = (None,)):
+                 max_active: int = 512, autostart: bool = True, lanes: tuple = (None,),
+                 pool_share: float = 0.2):
         """lanes: the largest n of each lane in increasing order, the last one
-        None (no bound); the default is one lane for every size."""
+        None (no bound); the default is one lane for every size.  pool_share:
+        the fraction of the budget that each lane's context may keep pooled
+        (memory of finished solves kept for the next ones instead of freed)."""
         lanes = tuple(lanes)
         if not lanes or lanes[-1] is not None or any(a is None for a in lanes[:-1]) or any(
                 a >= b for a, b in zip(lanes[:-2], lanes[1:-1])):
@@ -79,13 +82,17 @@ class Server:
         self.device = torch.device("cuda", device)
         if hbm_budget is None:
             free, _total = torch.cuda.mem_get_info(device)
-            hbm_budget = int(free * 0.6)  # the rest holds queued inputs and returned outputs
+            hbm_budget = int(free * 0.45)  # the rest holds pooled memory, queued inputs and returned outputs
         self.hbm_budget = hbm_budget
         self.iters_per_step = iters_per_step
         self.max_active = max_active
         self._lock = threading.Condition()
         self._stop = False
         self._lanes = [_Lane(self, device, nmax) for nmax in lanes]
+        # each lane's context keeps the memory of finished solves pooled for
+        # the next ones, up to its share of the budget
+        for lane in self._lanes:
+            lane.ctx.set_pool_limit(int(hbm_budget * pool_share))
         self.ctx = self._lanes[0].ctx  # for footprint queries
         self.in_use = 0
         self.pending_bytes = 0
@@ -102,7 +109,7 @@ class Server:
     # -- client side ----------------------------------------------------------
     def submit(self, s: torch.Tensor, tau: float, tol: float, **kw) -> Future:
         req = Request(s=s, tau=tau, tol=tol, **kw)
-        req.footprint = self.ctx.footprint(s.shape[0], req.leaf, req.prec, req.maxit, req.single)
+        req.footprint = self.reservation(s.shape[0], req.leaf, req.prec, req.maxit, req.single)
         if req.footprint == 0 or req.footprint > self.hbm_budget:
             req.future.set_exception(ValueError(f"request needs {req.footprint} bytes; budget {self.hbm_budget}"))
             return req.future
@@ -120,6 +127,13 @@ class Server:
             self.stats["max_pending"] = max(self.stats["max_pending"], npend)
             self._lock.notify_all()
         return req.future
+
+    def reservation(self, n: int, leaf: int, prec: str = "f64", maxit: int = 40, single: bool = False) -> int:
+        """Device bytes admission reserves for a request: its footprint plus
+        what a pooled memory block may hold beyond it (a quarter and 16 MiB);
+        0 for invalid arguments."""
+        fp = self.ctx.footprint(n, leaf, prec, maxit, single)
+        return fp + fp // 4 + (16 << 20) if fp > 0 else 0
 
     def backlog(self) -> tuple[int, int]:
         """(requests, input bytes) submitted and not yet admitted."""

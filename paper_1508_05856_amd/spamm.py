@@ -29,7 +29,7 @@ EXPORTS = ("spamm_create", "spamm_destroy", "spamm_last_error", "spamm_pyramid_l
            "spamm_multiply", "ns_sqrt", "spamm_ns_history", "spamm_solve_footprint", "spamm_solve_begin",
            "spamm_solve_step", "spamm_solve_poll", "spamm_solve_finish", "spamm_set_graphs", "spamm_profile_enable",
            "spamm_profile_read", "spamm_profile_reset", "spamm_solve_triples", "spamm_product_rep",
-           "spamm_multiply_noalloc", "spamm_alloc_count")
+           "spamm_multiply_noalloc", "spamm_alloc_count", "spamm_set_pool_limit")
 MAX_SLICES = 16
 KIND_GEMM, KIND_CULL, KIND_PYRAMID = 0, 1, 2
 
@@ -113,6 +113,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         lib.spamm_profile_read.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
         lib.spamm_alloc_count.argtypes = [vp]
         lib.spamm_alloc_count.restype = ctypes.c_int64
+        lib.spamm_set_pool_limit.argtypes = [vp, ctypes.c_size_t]
+        lib.spamm_set_pool_limit.restype = ctypes.c_int
         for f in (lib.spamm_create, lib.spamm_destroy, lib.spamm_norms, lib.spamm_multiply, lib.ns_sqrt,
                   lib.spamm_ns_history, lib.spamm_profile_enable, lib.spamm_profile_reset,
                   lib.spamm_profile_read, lib.spamm_solve_begin, lib.spamm_solve_step, lib.spamm_solve_poll,
@@ -303,6 +305,11 @@ class Context:
 
     def profile(self, enable: bool = True):
         _check(self.lib.spamm_profile_enable(self.handle, int(bool(enable))))
+
+    def set_pool_limit(self, nbytes: int):
+        """Device bytes the context keeps pooled at most (beyond it, returned
+        memory is freed)."""
+        _check(self.lib.spamm_set_pool_limit(self.handle, int(nbytes)))
 
     def alloc_count(self) -> int:
         """Device and pinned allocations this context has made so far."""

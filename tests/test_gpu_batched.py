@@ -295,3 +295,23 @@ def test_warm_context_steps_and_finishes_without_allocating():
         assert torch.equal(YB, first[2][0]) and torch.equal(ZB, first[2][1])
     finally:
         c.close()
+
+
+def test_pool_limit_frees_returned_memory():
+    """With a pool limit of zero a finished solve's memory is freed at once,
+    so the next solve allocates again; with the default (no limit) it is
+    reused.  Results are the same either way."""
+    from paper_1508_05856_amd import spamm
+    c = spamm.Context(0)
+    try:
+        s = dev(inputs.kms(400, 0.7))
+        Y0, Z0, _ = c.ns_sqrt(s, 1e-8, 1e-9, 20, leaf=32, stagnation_stop=True)
+        a = c.alloc_count()
+        Y1, Z1, _ = c.ns_sqrt(s, 1e-8, 1e-9, 20, leaf=32, stagnation_stop=True)
+        assert c.alloc_count() == a
+        c.set_pool_limit(0)
+        Y2, Z2, _ = c.ns_sqrt(s, 1e-8, 1e-9, 20, leaf=32, stagnation_stop=True)
+        assert c.alloc_count() > a
+        assert torch.equal(Y0, Y1) and torch.equal(Y0, Y2) and torch.equal(Z0, Z2)
+    finally:
+        c.close()

@@ -85,7 +85,7 @@ def test_requests_joining_a_running_mix_match_solo(solo_results, lanes):
 def test_admission_by_footprint(solo_results):
     from paper_1508_05856_amd import serve
     probe = serve.Server(0, autostart=False)
-    fp = [probe.ctx.footprint(REQS[i][1], REQS[i][4], "f64", 40) for i in (4, 6)]
+    fp = [probe.reservation(REQS[i][1], REQS[i][4], "f64", 40) for i in (4, 6)]
     probe.close()
     # room for either request alone but not both: they must run one after the other
     srv = serve.Server(0, hbm_budget=max(fp) + min(fp) // 2, iters_per_step=2, autostart=False)

@@ -120,6 +120,35 @@ def test_multiply_matches_oracle(ctx, tau, n, leaf):
     assert stats["thr"] == pytest.approx(tau * np.linalg.norm(a) * np.linalg.norm(b), rel=1e-13)
 
 
+@pytest.mark.parametrize("n", [2600, 2112])
+def test_multiply_large_tables_match_oracle(ctx, n):
+    """FP64 products of tables past the one-launch front (more than 1024 tiles
+    of 64, the parallel cull and multi-block longest-first sort): nb = 41
+    (n not a multiple of 64, a ragged last row and column of tiles) and
+    nb = 33.  Retained counts per tile equal the oracle's (ties excluded),
+    tiles to 1e-13 of ||A|| ||B|| on a sample of rows, columns and the
+    ragged corner."""
+    leaf, tau = 64, 1e-7
+    a = decaying(n, seed=11, rate=0.02)
+    b = decaying(n, seed=12, rate=0.03)
+    C, stats, trip = ctx.spamm_multiply(dev(a), dev(b), tau, leaf, triples=True)
+    nb = -(-n // leaf)
+    assert nb * nb > 1024 and 0 < stats["retained"] < nb ** 3
+    ties = near_tie_mask(a, b, leaf, tau)
+    per_tile = {}
+    for (i, j, k) in host(trip).tolist():
+        per_tile[(i, j)] = per_tile.get((i, j), 0) + 1
+    tiles = [(0, 0), (1, 2), (7, 8), (nb - 1, nb - 1), (nb - 2, nb - 1), (nb - 1, 0), (20, 21), (32, 31)]
+    out, counts = oracle.spamm_tiles(a, b, leaf, tau, tiles)
+    Ch = host(C)
+    scale = np.linalg.norm(a) * np.linalg.norm(b)
+    for (i, j), o, cnt in zip(tiles, out, counts):
+        if not ties[i, j].any():
+            assert per_tile.get((i, j), 0) == cnt, (i, j)
+        g_ = Ch[i * leaf:(i + 1) * leaf, j * leaf:(j + 1) * leaf]
+        assert np.abs(g_ - o[:g_.shape[0], :g_.shape[1]]).max() <= 1e-13 * scale, (i, j)
+
+
 def test_multiply_block_diagonal_and_limits(ctx):
     b, nb = 32, 8
     n = b * nb
@@ -462,3 +491,50 @@ def test_ns_bf16x3_leaves_error_vs_fp64_oracle(ctx, kind):
           f"vs {ores['iterations']}")
     assert info["status"] in (0, 2)
     assert ey <= bound and ez <= bound
+
+@pytest.fixture(scope="module")
+def c2_oracle_tau8():
+    """The oracle's whole n = 4096 solve at tau = 1e-8 (stagnation stop), as
+    the benchmark runs it: about 20 s on 16 host cores."""
+    s = inputs.config_c2(1e-8)["s"]
+    return s, oracle.ns_sqrt(s, 64, 1e-8, 1e-10, 40, stagnation_stop=True)
+
+
+def test_c2_whole_solve_matches_oracle(ctx, c2_oracle_tau8):
+    """The full-size n = 4096 solve at tau = 1e-8, FP64 leaves: status, update
+    count and retained-triple history equal to the oracle's, Y and Z within
+    1e-12 (relative Frobenius) of its whole solve (Sec. 3.2, eq. "cannonical")."""
+    s, o = c2_oracle_tau8
+    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-8, 1e-10, 40, leaf=64, stagnation_stop=True)
+    r, t, nR = ctx.ns_history()
+    assert info["status"] == o["status"] and info["iterations"] == o["iterations"]
+    np.testing.assert_array_equal(nR, o["nR"][:len(nR)])
+    ey, ez = rel(host(Y), o["Y"]), rel(host(Z), o["Z"])
+    print(f"n=4096 tau=1e-8 FP64: relY {ey:.2e} relZ {ez:.2e}")
+    assert ey <= 1e-12 and ez <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x6"])
+def test_c2_reduced_precision_whole_solve_vs_oracle(ctx, c2_oracle_tau8, prec):
+    """The same full-size solve with FP32 and BF16x6 leaves against the
+    oracle's FP64 roots (kappa ~ 3.5e4).  BF16x6 measures Y 5.5e-6, Z 1.8e-5:
+    Y is held to 1e-5, as on the ill-conditioned analogue (the bf16 matrix
+    core drops the bits of its block sums below FP32 precision of the largest
+    product, toward zero; test_gpu_mfma_rounding), Z to four times what
+    rounding s' to FP32 alone costs s'^{-1/2} (1.0e-5 here).  FP32 leaves
+    accumulate across the whole retained k list in FP32 on the same kind of
+    matrix core and measure Y 1.1e-5, Z 1.7e-4: both held to
+    sqrt(kappa) 2^-19 (3.6e-4)."""
+    s, o = c2_oracle_tau8
+    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-8, 1e-10, 40, leaf=64, prec=prec, stagnation_stop=True)
+    ey, ez = rel(host(Y), o["Y"]), rel(host(Z), o["Z"])
+    floor = fp32_storage_floor(s)
+    print(f"n=4096 tau=1e-8 {prec}: relY {ey:.2e} relZ {ez:.2e} (FP32 storage floor of Z {floor:.2e}); "
+          f"iterations {info['iterations']} vs {o['iterations']}")
+    assert info["status"] in (0, 2)
+    w = np.linalg.eigvalsh(s)
+    if prec == "bf16x6":
+        assert ey <= 1e-5 and ez <= 4.0 * floor
+    else:
+        bound = np.sqrt(w[-1] / w[0]) * 2.0 ** -19
+        assert ey <= bound and ez <= bound
