@@ -328,15 +328,16 @@ def run_serving(args):
                                     "exact_sample_size": len(rex),
                                     "meeting_tol_1e-8": sum(1 for x in rin if x < 1e-8)}
 
-    # the same stream one request at a time: each request's service time,
-    # then first-come first-served from its arrival
+    # the same stream one request at a time: each request's service time (its
+    # input built on the device, as the served run's client does at arrival,
+    # then its solve), then first-come first-served from its arrival
     one = None
     if not args.no_one_at_a_time:
         service = []
         for r in reqs:
-            s = inputs.build_spec_device(r, dev)
             torch.cuda.synchronize()
             ts = time.perf_counter()
+            s = inputs.build_spec_device(r, dev)
             _, _, info = ctx.ns_sqrt(s, r["tau"], 1e-8, tau_s=0.01 * r["tau"], raise_on_error=False, **opts)
             service.append(time.perf_counter() - ts)
             del s
