@@ -91,7 +91,8 @@ def parse():
     p.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     p.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     p.add_argument("--nmax", type=int, default=16384, help="serving: largest n (log-uniform from 512)")
-    p.add_argument("--iters-per-step", type=int, default=4, help="batched: iterations per synchronisation")
+    p.add_argument("--iters-per-step", default="4", help="batched: iterations per synchronisation; serving: "
+                   "one value or one per lane, comma-separated")
     p.add_argument("--pool-share", type=float, default=0.2,
                    help="serving: fraction of the admission budget each lane may keep pooled")
     p.add_argument("--no-one-at-a-time", action="store_true",
@@ -133,7 +134,7 @@ def run_batched(args):
         solves = [ctx.solve_begin(m, sp["tau"], tol, maxit, leaf=lf, prec=prec, tau_s=tsr * sp["tau"],
                                   stagnation_stop=True)
                   for m, sp, lf in zip(mats, specs, leaves)]
-        while ctx.solve_step(solves, args.iters_per_step) > 0:
+        while ctx.solve_step(solves, int(args.iters_per_step)) > 0:
             pass
         return [sv.finish(Y, Z)[2] for sv, (Y, Z) in zip(solves, outs)]
 
@@ -187,7 +188,7 @@ def run_batched(args):
             "taus": sorted({sp["tau"] for sp in specs}), "tau_s": "0.01 tau", "tol": tol, "maxit": maxit,
             "stop": "stagnation",
             "precision": prec, "leaves": {str(b): leaves.count(b) for b in sorted(set(leaves))},
-            "iters_per_step": args.iters_per_step, "graphs": True,
+            "iters_per_step": int(args.iters_per_step), "graphs": True,
             "valid_solves": nvalid, "diverged": diverged,
             "one_at_a_time_solves_per_s": nvalid / t_single, "speedup_vs_one_at_a_time": t_single / t_batched,
             "statuses": {str(k): [i["status"] for i in infos].count(k) for k in sorted({i["status"] for i in infos})},
@@ -224,7 +225,8 @@ def run_serving(args):
     dev = torch.device("cuda:0")
     lanes = tuple(int(x) for x in args.lanes.split(",") if x) + (None,)
     opts = dict(maxit=40, leaf=64, prec="f64", stagnation_stop=True)
-    srv = serve.Server(0, iters_per_step=args.iters_per_step, lanes=lanes, pool_share=args.pool_share)
+    its = [int(x) for x in str(args.iters_per_step).split(",")]
+    srv = serve.Server(0, iters_per_step=its if len(its) > 1 else its[0], lanes=lanes, pool_share=args.pool_share)
     # warm up kernels and tables on a tiny stream
     for f in [srv.submit(inputs.kms_device(n, 0.7, dev), 1e-6, 1e-8, leaf=64) for n in (512, 1024)]:
         f.result()
@@ -363,7 +365,7 @@ def run_serving(args):
             "answered_per_s": len(results) / t_end, "offered_rate": args.rate, "duration_s": args.duration,
             "makespan_s": t_end, "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
-            "tol": 1e-8, "tau_s": "0.01 tau", "stop": "stagnation", "iters_per_step": args.iters_per_step,
+            "tol": 1e-8, "tau_s": "0.01 tau", "stop": "stagnation", "iters_per_step": its,
             "lanes": [x if x is not None else "rest" for x in lanes],
             "sizes_n": [int(min(r["n"] for r in reqs)), int(max(r["n"] for r in reqs))],
             "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},

@@ -58,8 +58,9 @@ class Result:
 
 
 class _Lane:
-    def __init__(self, server: "Server", device: int, nmax: int | None):
+    def __init__(self, server: "Server", device: int, nmax: int | None, iters: int):
         self.nmax = nmax  # largest n this lane takes (None: no bound)
+        self.iters = iters  # iterations per step
         self.ctx = spamm.Context(device)
         self.stream = torch.cuda.Stream(device)  # default priority
         self.pending: collections.deque[Request] = collections.deque()
@@ -68,11 +69,12 @@ class _Lane:
 
 
 class Server:
-    def __init__(self, device: int = 0, hbm_budget: int | None = None, iters_per_step: int = 2,
+    def __init__(self, device: int = 0, hbm_budget: int | None = None, iters_per_step=2,
                  max_active: int = 512, autostart: bool = True, lanes: tuple = (None,),
                  pool_share: float = 0.2):
         """lanes: the largest n of each lane in increasing order, the last one
-        None (no bound); the default is one lane for every size.  pool_share:
+        None (no bound); the default is one lane for every size.
+        iters_per_step: iterations per step, one number or one per lane.  pool_share:
         the fraction of the budget that each lane's context may keep pooled
         (memory of finished solves kept for the next ones instead of freed)."""
         lanes = tuple(lanes)
@@ -84,11 +86,14 @@ class Server:
             free, _total = torch.cuda.mem_get_info(device)
             hbm_budget = int(free * 0.45)  # the rest holds pooled memory, queued inputs and returned outputs
         self.hbm_budget = hbm_budget
-        self.iters_per_step = iters_per_step
+        its = tuple(iters_per_step) if isinstance(iters_per_step, (tuple, list)) else (iters_per_step,) * len(lanes)
+        if len(its) != len(lanes) or min(its) < 1:
+            raise ValueError("iters_per_step must be >= 1, one value or one per lane")
+        self.iters_per_step = its
         self.max_active = max_active
         self._lock = threading.Condition()
         self._stop = False
-        self._lanes = [_Lane(self, device, nmax) for nmax in lanes]
+        self._lanes = [_Lane(self, device, nmax, it) for nmax, it in zip(lanes, its)]
         # each lane's context keeps the memory of finished solves pooled for
         # the next ones, up to its share of the budget
         for lane in self._lanes:
@@ -217,7 +222,7 @@ class Server:
             with self._lock:
                 self.stats["max_active"] = max(self.stats["max_active"], sum(len(ln.active) for ln in self._lanes))
             try:
-                lane.ctx.solve_step([sv for _, sv, _ in lane.active], self.iters_per_step)
+                lane.ctx.solve_step([sv for _, sv, _ in lane.active], lane.iters)
             except Exception as e:
                 self._fail_active(lane, e)
                 continue

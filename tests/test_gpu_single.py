@@ -62,7 +62,7 @@ def test_single_channel_matches_oracle(ctx, case):
     assert rel(Y.cpu().numpy(), o["Y"]) <= 1e-12 and rel(Z.cpu().numpy(), o["Z"]) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x6"])
 def test_single_and_dual_in_one_step_match_solo(ctx, prec):
     mats = [inputs.kms(300, 0.7), inputs.gauss_gramian(8, 1.0), inputs.kms(500, 0.85), inputs.gauss_gramian(6, 1.2)]
     single = [True, False, True, False]
@@ -95,3 +95,16 @@ def test_single_footprint_holds_the_transpose(ctx):
     dual = ctx.footprint(2048, 64, "f64", 40)
     single = ctx.footprint(2048, 64, "f64", 40, single=True)
     assert single - dual >= 2048 * 2048 * 8
+
+
+@pytest.mark.parametrize("leaf", [32, 64])
+def test_single_channel_bf16x6_error(ctx, leaf):
+    """The single-channel instance with BF16x6 leaves (the one-tile split
+    kernel at both leaf sizes) against the FP64 oracle: Y and Z within 5e-6
+    on the KMS matrix (kappa 32)."""
+    s = inputs.kms(512, 0.7)
+    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-8, 1e-5, 40, leaf=leaf, prec="bf16x6", stagnation_stop=True, single=True)
+    o = oracle.ns_sqrt(s, leaf, 1e-8, 1e-5, 40, stagnation_stop=True, single=True)
+    ey, ez = rel(Y.cpu().numpy(), o["Y"]), rel(Z.cpu().numpy(), o["Z"])
+    print(f"single bf16x6 leaf {leaf}: relY {ey:.2e} relZ {ez:.2e}")
+    assert ey <= 5e-6 and ez <= 5e-6

@@ -170,6 +170,32 @@ def test_multiply_capacity_error(ctx):
     assert e.value.status == spamm.ECAPACITY
 
 
+@pytest.mark.parametrize("n,leaf", [(500, 32), (640, 64), (1630, 64)])
+def test_multiply_bf16x6_error_vs_oracle(ctx, n, leaf):
+    """One BF16x6 product (FP32 operands split into three bf16 pieces, six
+    products, FP64 sums of the 32-k slices) against the oracle's FP64
+    product of the same FP32-rounded operands: every tile within 32 FP32
+    units (2^-24) of the tile's own scale, the sum over its retained k of
+    ||A_ik|| ||B_kj||.  Each 32-k slice sum carries one FP32 rounding and the
+    bits the matrix core drops below its largest product; BF16x3 is held to
+    2^-13 of the whole product."""
+    tau = 1e-6
+    a = decaying(n, seed=9, rate=0.05).astype(np.float32).astype(np.float64)
+    b = decaying(n, seed=10, rate=0.07).astype(np.float32).astype(np.float64)
+    C, st, _ = ctx.spamm_multiply(dev(a), dev(b), tau, leaf, prec="bf16x6")
+    Co, Ro, cnt = oracle.spamm(a, b, leaf, tau)
+    nb = -(-n // leaf)
+    la, lb = oracle.norms(a, leaf)[0][:nb, :nb], oracle.norms(b, leaf)[0][:nb, :nb]
+    scale = np.zeros((nb, nb))
+    for (i, j, k) in Ro.tolist():
+        scale[i, j] += la[i, k] * lb[k, j]
+    Ch = host(C)
+    for i in range(nb):
+        for j in range(nb):
+            e = np.abs(Ch[i * leaf:(i + 1) * leaf, j * leaf:(j + 1) * leaf] - Co[i * leaf:(i + 1) * leaf, j * leaf:(j + 1) * leaf]).max()
+            assert e <= 32 * 2.0 ** -24 * scale[i, j] + 1e-300, (i, j, e, scale[i, j])
+
+
 def test_multiply_f32_error_vs_oracle(ctx):
     n, leaf, tau = 512, 32, 1e-6
     a = decaying(n, seed=7, rate=0.05)
