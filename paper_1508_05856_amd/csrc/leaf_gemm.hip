@@ -521,8 +521,10 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
 
 // ---------------------------------------------------------------------------
 // BF16x3 leaf products of 64x64 tiles, one workgroup per quad of output tiles
-// (2i+di, 2j+dj).  Wave w = 2di+dj owns tile (di, dj) whole (4x4 blocks of
-// 16x16).  The workgroup first merges the four retained lists into their
+// (2i+di, 2j+dj), eight waves: waves 2t and 2t+1 own rows 0-31 and 32-63 of
+// tile t = 2di+dj (2x4 blocks of 16x16 each), so four waves per SIMD fit and
+// the staging of a stage is spread over 512 threads (one A chunk and one B
+// unit each).  The workgroup first merges the four retained lists into their
 // union in LDS (increasing k, with a 4-bit mask of the tiles that retain k),
 // then runs the two-stage-ahead pipeline over the union: a stage stages A_ik
 // of each row half and B_kj of each column half that some tile of the mask
@@ -540,36 +542,39 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
 // ---------------------------------------------------------------------------
 struct Bf3Quad {
     static constexpr int B = 64;
-    static constexpr int NT = 256;
+    static constexpr int NT = 512;  // eight waves, two per tile
     static constexpr int KS = 32;
     static constexpr int SPT = B / KS;
     static constexpr int LDA = KS;      // swizzled, unpadded
     static constexpr int LDB = KS + 8;  // padded
-    static constexpr int A_CH = B * KS / 4 / NT;         // float4 chunks of one A half per thread per stage
-    static constexpr int B_UN = (KS / 2) * (B / 4) / NT;  // (k pair, 4 columns) units of one B half per thread
+    static constexpr int A_CH = B * KS / 4 / NT;               // float4 chunks of one A half per thread per stage
+    static constexpr int B_UN = 2 * (KS / 2) * (B / 4) / NT;  // (k pair, 4 columns) units of both B halves per thread
 };
-static_assert(Bf3Quad::A_CH == 2 && Bf3Quad::B_UN == 1, "stage split assumed below");
+static_assert(Bf3Quad::A_CH == 1 && Bf3Quad::B_UN == 1, "stage split assumed below");
 
 __device__ inline int swz_a(int row, int k) {  // bf16 offset of (row, k) in an A plane
     return row * Bf3Quad::LDA + ((((k >> 3) ^ (row >> 2)) & 3) << 3) + (k & 7);
 }
 
-__global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restrict__ jobs,
-                                                           const int32_t *__restrict__ work_count) {
+// At most 128 registers per lane, so that two workgroups (four waves per SIMD) share a CU.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_leaf_gemm_bf3_quad(
+    const Job *__restrict__ jobs, const int32_t *__restrict__ work_count) {
     using C = Bf3Quad;
     constexpr int B = C::B;
-    constexpr int NP = 2;  // BF16x3 pieces
-    // [buffer][row half di / column half dj][plane][...]
+    constexpr int NT = C::NT;
+    constexpr int NP = 2;
     __shared__ __attribute__((aligned(16))) __bf16 As[2][2][NP][B * C::LDA];
     __shared__ __attribute__((aligned(16))) __bf16 Bt[2][2][NP][B * C::LDB];
-    __shared__ unsigned umask[QUAD_NB_MAX / 4];  // byte k%4 of word k/4: tiles retaining k
-    __shared__ unsigned ulist[QUAD_NB_MAX];      // k | mask << 16, increasing k
-    __shared__ int wtot[4];
+    __shared__ unsigned umask[QUAD_NB_MAX / 4];
+    __shared__ unsigned ulist[QUAD_NB_MAX];
+    __shared__ int wtot[8];
+    __shared__ double red[4][3][4];  // [tile][norm, r2, trace][quadrant]
 
     const int nwork = *work_count;
     if ((int)blockIdx.x >= nwork) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const Job J = jobs[4 * blockIdx.x + w];  // this wave's tile
+    const int t = w >> 1, rh = w & 1;  // tile of the quad, row half of the tile
+    const Job J = jobs[4 * blockIdx.x + t];
     const int nb = jobs[4 * blockIdx.x].nb;
     const gptr<const float> Arow[2] = {to_global((const float *)jobs[4 * blockIdx.x].a_row),
                                        to_global((const float *)jobs[4 * blockIdx.x + 2].a_row)};
@@ -577,19 +582,18 @@ __global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restric
                                        to_global((const float *)jobs[4 * blockIdx.x + 1].b_col)};
     constexpr int64_t TS = (int64_t)B * B;
 
-    // union of the four retained lists
+    // union of the four retained lists (the first wave of each tile adds its bit)
     const int nwords = (nb + 3) / 4;
-    for (int x = tid; x < nwords; x += C::NT) umask[x] = 0u;
+    for (int x = tid; x < nwords; x += NT) umask[x] = 0u;
     __syncthreads();
-    if (J.cnt > 0) {
+    if (rh == 0 && J.cnt > 0) {
         const gptr<const int32_t> list = to_global(J.list);
         for (int e = lane; e < J.cnt; e += 64) {
             const int k = list[e];
-            atomicOr(&umask[k >> 2], 1u << (8 * (k & 3) + w));
+            atomicOr(&umask[k >> 2], 1u << (8 * (k & 3) + t));
         }
     }
     __syncthreads();
-    // one word (4 consecutive k) per thread: nb <= QUAD_NB_MAX = 4 * NT
     const unsigned word = tid < nwords ? umask[tid] : 0u;
     const int mine = (int)((word & 0xffu) != 0) + (int)((word & 0xff00u) != 0) + (int)((word & 0xff0000u) != 0) +
                      (int)((word & 0xff000000u) != 0);
@@ -603,7 +607,9 @@ __global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restric
     __syncthreads();
     int pos = incl - mine;
     for (int x = 0; x < w; ++x) pos += wtot[x];
-    const int U = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    int U = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) U += wtot[x];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const unsigned m = (word >> (8 * q)) & 0xfu;
@@ -612,83 +618,73 @@ __global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restric
     __syncthreads();
 
     const int S = U * C::SPT;
-    const int di = w >> 1, dj = w & 1;
+    const int di = t >> 1, dj = t & 1;
+    const int hb = tid >> 8;          // the B column half this thread stages
+    const int ub = tid & 255;         // its (k pair, 4 columns) unit of that half
+    const int kp = ub % (C::KS / 2), cg = ub / (C::KS / 2);
 
-    v4f acc[4][4];
+    v4f acc[2][4];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0.0f;
 
-    // operands a half needs: A row half h for tiles 2h, 2h+1; B column half h for tiles h, h+2
     auto needA = [](unsigned m, int h) { return (m & (h ? 0xcu : 0x3u)) != 0u; };
     auto needB = [](unsigned m, int h) { return (m & (h ? 0xau : 0x5u)) != 0u; };
-    // registers of one stage: [0..3] A halves 0, 1 (A_CH chunks each), [4..7] B halves 0, 1 (rows 2kp, 2kp+1)
+    // registers of one stage: [0], [1] one chunk of A halves 0, 1; [2], [3] rows 2kp, 2kp+1 of this thread's B unit
     auto gload = [&](int s, v4f *r) {
         const unsigned e = ulist[s / C::SPT];
         const int k = (int)(e & 0xffffu);
         const unsigned m = e >> 16;
         const int ks = s % C::SPT;
+        const int el = tid * 4;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 2; ++h)
             if (needA(m, h)) {
                 const gptr<const float> a = Arow[h] + (int64_t)k * TS + ks * C::KS;
-#pragma unroll
-                for (int c = 0; c < C::A_CH; ++c) {
-                    const int el = (tid + c * C::NT) * 4;
-                    r[2 * h + c] = *(gptr<const v4f>)(a + (el / C::KS) * B + el % C::KS);
-                }
+                r[h] = *(gptr<const v4f>)(a + (el / C::KS) * B + el % C::KS);
             }
-            if (needB(m, h)) {
-                const gptr<const float> b = Bcol[h] + (int64_t)k * nb * TS + (int64_t)ks * C::KS * B;
-                const int kp = tid % (C::KS / 2), cg = tid / (C::KS / 2);
-                r[4 + 2 * h] = *(gptr<const v4f>)(b + (2 * kp) * B + 4 * cg);
-                r[5 + 2 * h] = *(gptr<const v4f>)(b + (2 * kp + 1) * B + 4 * cg);
-            }
+        if (needB(m, hb)) {
+            const gptr<const float> b = Bcol[hb] + (int64_t)k * nb * TS + (int64_t)ks * C::KS * B;
+            r[2] = *(gptr<const v4f>)(b + (2 * kp) * B + 4 * cg);
+            r[3] = *(gptr<const v4f>)(b + (2 * kp + 1) * B + 4 * cg);
         }
     };
     auto sstore = [&](int buf, int s, const v4f *r) {
         const unsigned m = ulist[s / C::SPT] >> 16;
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        const int el = tid * 4;
+        const int row = el / C::KS, k = el % C::KS;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 2; ++h)
             if (needA(m, h)) {
+                unsigned p0[NP], p1[NP];
+                split_pair<NP>(r[h][0], r[h][1], p0);
+                split_pair<NP>(r[h][2], r[h][3], p1);
 #pragma unroll
-                for (int c = 0; c < C::A_CH; ++c) {
-                    const int el = (tid + c * C::NT) * 4;
-                    const int row = el / C::KS, k = el % C::KS;
-                    unsigned p0[NP], p1[NP];
-                    split_pair<NP>(r[2 * h + c][0], r[2 * h + c][1], p0);
-                    split_pair<NP>(r[2 * h + c][2], r[2 * h + c][3], p1);
-#pragma unroll
-                    for (int x = 0; x < NP; ++x) *(u2 *)&As[buf][h][x][swz_a(row, k)] = u2{p0[x], p1[x]};
-                }
+                for (int x = 0; x < NP; ++x) *(u2 *)&As[buf][h][x][swz_a(row, k)] = u2{p0[x], p1[x]};
             }
-            if (needB(m, h)) {
-                const int kp = tid % (C::KS / 2), cg = tid / (C::KS / 2);
+        if (needB(m, hb)) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    unsigned pp[NP];
-                    split_pair<NP>(r[4 + 2 * h][q], r[5 + 2 * h][q], pp);  // (k, k+1) of column 4cg+q
-                    const int col = 4 * cg + q;
+            for (int q = 0; q < 4; ++q) {
+                unsigned pp[NP];
+                split_pair<NP>(r[2][q], r[3][q], pp);  // (k, k+1) of column 4cg+q
+                const int col = 4 * cg + q;
 #pragma unroll
-                    for (int x = 0; x < NP; ++x) *(unsigned *)&Bt[buf][h][x][col * C::LDB + 2 * kp] = pp[x];
-                }
+                for (int x = 0; x < NP; ++x) *(unsigned *)&Bt[buf][hb][x][col * C::LDB + 2 * kp] = pp[x];
             }
         }
     };
     auto compute = [&](int buf, int s) {
         const unsigned m = ulist[s / C::SPT] >> 16;
-        if (!((m >> w) & 1u)) return;
-        // operand layout of the 16x16x32 bf16 MFMA: lane l supplies row (A) or
-        // column (B) l%16 at k = 8(l/16) .. 8(l/16)+7
+        if (!((m >> t) & 1u)) return;
         const int ko = 8 * (lane >> 4);
-        bf16x8 af[4][NP];
+        bf16x8 af[2][NP];
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi) {
-            const int row = bi * 16 + (lane & 15);
+        for (int bi = 0; bi < 2; ++bi) {
+            const int row = rh * 32 + bi * 16 + (lane & 15);
 #pragma unroll
             for (int x = 0; x < NP; ++x) af[bi][x] = *(const bf16x8 *)&As[buf][di][x][swz_a(row, ko)];
         }
@@ -699,11 +695,11 @@ __global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restric
 #pragma unroll
             for (int x = 0; x < NP; ++x) bf[x] = *(const bf16x8 *)&Bt[buf][dj][x][col * C::LDB + ko];
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) acc[bi][bj] = mma_split<NP>(af[bi], bf, acc[bi][bj]);
+            for (int bi = 0; bi < 2; ++bi) acc[bi][bj] = mma_split<NP>(af[bi], bf, acc[bi][bj]);
         }
     };
 
-    v4f r0[8], r1[8];
+    v4f r0[4], r1[4];
     if (S > 0) {
         gload(0, r0);
         if (S > 1) gload(1, r1);
@@ -723,49 +719,59 @@ __global__ __launch_bounds__(256) void k_leaf_gemm_bf3_quad(const Job *__restric
         __syncthreads();
     }
 
-    // epilogue, per wave: its tile (FP32), FP64 norm and Newton-Schulz
-    // partials, each summed per 32x32 quadrant then over the quadrants in order
-    if (J.cnt < 0) return;  // past the edge
+    // epilogue: this wave's two quadrants (rh, 0) and (rh, 1) of its tile
+    const bool live = J.cnt >= 0;  // tiles past the edge write nothing
     const bool nsx = J.part != nullptr;
     const gptr<float> Ct = to_global((float *)J.c);
-    double qa = 0.0, r2a = 0.0, tra = 0.0;
 #pragma unroll
-    for (int quad = 0; quad < 4; ++quad) {
-        const int wr = quad >> 1, wc = quad & 1;
+    for (int wc = 0; wc < 2; ++wc) {
         double qs = 0.0, r2 = 0.0, tr = 0.0;
+        if (live) {
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+            for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
+                for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = wr * 32 + bi * 16 + 4 * (lane >> 4) + r;
-                    const int col = wc * 32 + bj * 16 + (lane & 15);
-                    const double x = (double)acc[2 * wr + bi][2 * wc + bj][r];
-                    float out;
-                    if (nsx) {
-                        const int64_t gi = (int64_t)J.i * B + row, gj = (int64_t)J.j * B + col;
-                        const bool diag = (gi == gj) && (gi < J.n);
-                        const bool logical = (gi < J.n) && (gj < J.n);
-                        const double h = (diag ? 1.5 : 0.0) - 0.5 * x;
-                        const double ex = (diag ? 1.0 : 0.0) - x;
-                        if (logical) r2 += ex * ex;
-                        if (diag) tr += x;
-                        out = J.fused_map ? (float)h : (float)x;
-                    } else {
-                        out = (float)x;
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rh * 32 + bi * 16 + 4 * (lane >> 4) + r;
+                        const int col = wc * 32 + bj * 16 + (lane & 15);
+                        const double x = (double)acc[bi][2 * wc + bj][r];
+                        float out;
+                        if (nsx) {
+                            const int64_t gi = (int64_t)J.i * B + row, gj = (int64_t)J.j * B + col;
+                            const bool diag = (gi == gj) && (gi < J.n);
+                            const bool logical = (gi < J.n) && (gj < J.n);
+                            const double h = (diag ? 1.5 : 0.0) - 0.5 * x;
+                            const double ex = (diag ? 1.0 : 0.0) - x;
+                            if (logical) r2 += ex * ex;
+                            if (diag) tr += x;
+                            out = J.fused_map ? (float)h : (float)x;
+                        } else {
+                            out = (float)x;
+                        }
+                        Ct[row * B + col] = out;
+                        const double dv = (double)out;
+                        qs += dv * dv;
                     }
-                    Ct[row * B + col] = out;
-                    const double dv = (double)out;
-                    qs += dv * dv;
-                }
-        qa += wave_sum(qs);
-        if (nsx) {
-            r2a += wave_sum(r2);
-            tra += wave_sum(tr);
+        }
+        qs = wave_sum(qs);
+        r2 = wave_sum(r2);
+        tr = wave_sum(tr);
+        if (lane == 0) {
+            red[t][0][2 * rh + wc] = qs;
+            red[t][1][2 * rh + wc] = r2;
+            red[t][2][2 * rh + wc] = tr;
         }
     }
-    if (lane == 0) {
+    __syncthreads();
+    if (live && rh == 0 && lane == 0) {
+        double qa = 0.0, r2a = 0.0, tra = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            qa += red[t][0][q];
+            r2a += red[t][1][q];
+            tra += red[t][2][q];
+        }
         *to_global(J.qc) = qa;
         if (nsx) {
             to_global(J.part)[0] = r2a;
