@@ -25,6 +25,14 @@ import torch
 from . import spamm
 
 
+def exact_residual(ctx: "spamm.Context", Y: torch.Tensor, Z: torch.Tensor) -> float:
+    """||I - Y Z||_F from the library's dense (tau = 0) FP64 product on the
+    current stream."""
+    C, _, _ = ctx.spamm_multiply(Y, Z, 0.0, 64)
+    C.diagonal().sub_(1.0)
+    return float(torch.linalg.norm(C))
+
+
 @dataclass
 class Request:
     s: torch.Tensor                 # device, float64, symmetric
@@ -38,6 +46,7 @@ class Request:
     stagnation_stop: bool = True
     damped: bool = False
     single: bool = False
+    verify: bool = False            # also return the exact ||I - Y Z||_F (a dense product) as info["resid_exact"]
     t_submit: float = 0.0
     future: Future = field(default_factory=Future)
     footprint: int = 0
@@ -244,6 +253,8 @@ class Server:
                     with self._lock:
                         self.stats["failed"] += 1
                     continue
+                if req.verify:
+                    info["resid_exact"] = exact_residual(lane.ctx, Y, Z) if info["status"] >= 0 else None
                 self._release(req.footprint)
                 now = time.perf_counter()
                 with self._lock:

@@ -160,3 +160,23 @@ def test_served_results_match_the_fp64_oracle():
         Y, Z = r.Y.cpu().numpy(), r.Z.cpu().numpy()
         assert np.linalg.norm(Y - o["Y"]) <= 1e-12 * np.linalg.norm(o["Y"]), (kind, n)
         assert np.linalg.norm(Z - o["Z"]) <= 1e-12 * np.linalg.norm(o["Z"]), (kind, n)
+
+
+def test_verified_answers_carry_the_exact_residual(solo_results):
+    """verify=True returns ||I - Y Z||_F of the answer, computed by the
+    server: equal to the residual of the solo result computed in FP64 on the
+    host, within the rounding bound of two dense products of length n
+    (2 n 2^-53 ||Y||_F ||Z||_F), and None for a diverged solve."""
+    from paper_1508_05856_amd import serve
+    srv = serve.Server(0, iters_per_step=2)
+    futs = [srv.submit(mat(kind, n, p, sd), tau, 1e-8, maxit=40, leaf=leaf, stagnation_stop=True, verify=True)
+            for kind, n, p, sd, leaf, tau in REQS]
+    results = [f.result(timeout=120) for f in futs]
+    srv.close()
+    for (kind, n, *_), r, (Y, Z, info) in zip(REQS, results, solo_results):
+        if info["status"] < 0:
+            assert r.info["resid_exact"] is None
+            continue
+        ref = np.linalg.norm(np.eye(n) - Y @ Z)
+        bound = 2 * n * 2.0 ** -53 * np.linalg.norm(Y) * np.linalg.norm(Z)
+        assert abs(r.info["resid_exact"] - ref) <= bound, (kind, n, r.info["resid_exact"], ref, bound)
