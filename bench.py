@@ -179,6 +179,7 @@ def run_batched(args):
     counted = [i["status"] >= 0 and r <= args.count_below for r, i in zip(resid, infos)]
     nvalid = sum(counted)
     diverged = [dict(kind=sp["kind"], n=sp["n"], tau=sp["tau"]) for sp, i in zip(specs, infos) if i["status"] < 0]
+    cpu = None if args.no_cpu_baseline else batched_cpu_baseline(specs, leaves, infos, nvalid, tol, maxit, tsr)
     line = {
         "metric": "NS sqrt solves/sec, 64 uneven SPD instances solved together (batched)",
         "value": nvalid / t_batched, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -209,8 +210,40 @@ def run_batched(args):
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "launches": int(len(gemm_ms)), "avg_launch_ms": float(np.mean(gemm_ms)),
                      "timing": "separate profiled pass with plain launches"},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def batched_cpu_baseline(specs, leaves, infos, counted, tol, maxit, tsr, budget_s=20.0):
+    """The oracle (FP64 leaves) on a sample of the batched instances: every
+    8th by size, smallest first, until about budget_s of CPU time.  Its flop
+    rate on the sample scales the whole batch's retained leaf products (the
+    GPU run's) to an estimated batch time."""
+    import oracle
+
+    from paper_1508_05856_amd import inputs
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["n"])
+    secs, flops, used = 0.0, 0.0, []
+    for i in order[::8]:
+        if secs > budget_s:
+            break
+        sp = specs[i]
+        a = inputs.build_spec(sp)
+        t0 = time.perf_counter()
+        o = oracle.ns_sqrt(a, leaves[i], sp["tau"], tol, maxit, tau_s=tsr * sp["tau"], stagnation_stop=True)
+        secs += time.perf_counter() - t0
+        flops += 2.0 * leaves[i] ** 3 * float(o["nR"].sum())
+        used.append(sp["n"])
+    rate = flops / secs
+    total = float(sum(i["flops_total"] for i in infos))
+    est = total / rate
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": counted / est, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"the oracle's whole solves of {len(used)} of the {len(specs)} instances (n = "
+                       f"{', '.join(map(str, used))}): {secs:.1f} s at {rate / 1e9:.2f} GFLOP/s of retained leaf "
+                       f"products; the batch's {total / 1e12:.2f} TFLOP at that rate take {est:.0f} s for its "
+                       f"{counted} counted solves")}
 
 
 def run_serving(args):
