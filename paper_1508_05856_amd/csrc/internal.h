@@ -100,8 +100,12 @@ constexpr int BF3_XCD_RUN = 64;
 // (2i..2i+1, 2j..2j+1): the quad's workgroup stages each A_ik and B_kj once
 // for the tiles of the quad that retain k.  The quad kernel keeps the union of
 // the four retained lists in LDS, for at most QUAD_NB_MAX tiles per side.
+// BF16x6 quads hold one workgroup per CU (three planes of LDS), so tables on
+// the one-launch front (at most FRONT_MAX tiles) keep one tile per workgroup.
 constexpr int QUAD_NB_MAX = 1024;
-inline bool quad_tiles(int gprec, int leaf) { return gprec == P_BF16X3 && leaf == 64; }
+inline bool quad_tiles(int gprec, int leaf, int total_tiles) {
+    return leaf == 64 && (gprec == P_BF16X3 || (gprec == P_BF16X6 && total_tiles > 1024));
+}
 
 // One output tile of one product, with every pointer already resolved for the
 // current parity, so a leaf-product workgroup starts with a single load.
@@ -176,7 +180,7 @@ hipError_t launch_fill_zero(double *p, int64_t count, hipStream_t st);
 // Batched stages over a product table.
 hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st);
 // Longest-first job list for the leaf products of precision gprec on leaf
-// tiles of side `leaf` (quads of tiles when quad_tiles(gprec, leaf)).
+// tiles of side `leaf` (quads of tiles when quad_tiles(gprec, leaf, total tiles)).
 hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st);
 hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t st);
 // Tables of at most FRONT_MAX tiles and FRONT_PRODS products (and not quad

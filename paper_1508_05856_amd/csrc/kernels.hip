@@ -876,7 +876,7 @@ __global__ __launch_bounds__(1024) void k_front_small(const ProdDesc *__restrict
 }
 
 bool front_small(const ProdTable &t, int leaf, int gprec) {
-    return t.total_tiles <= FRONT_MAX && t.nprod <= FRONT_PRODS && !quad_tiles(gprec, leaf);
+    return t.total_tiles <= FRONT_MAX && t.nprod <= FRONT_PRODS && !quad_tiles(gprec, leaf, t.total_tiles);
 }
 
 hipError_t launch_front_small(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
@@ -889,7 +889,7 @@ hipError_t launch_front_small(const ProdTable &t, int leaf, int gprec, hipStream
 
 hipError_t launch_plan_tab(const ProdTable &t, int leaf, int gprec, hipStream_t st) {
     const int esz = gprec == P_F64 ? 8 : 4;
-    const int quad = quad_tiles(gprec, leaf) ? 1 : 0;
+    const int quad = quad_tiles(gprec, leaf, t.total_tiles) ? 1 : 0;
     // FP64 products of large tables (beyond one-workgroup sorting) also run
     // in XCD runs: their operands stream from HBM, and neighbouring tiles of
     // a run share A rows and B columns in one L2

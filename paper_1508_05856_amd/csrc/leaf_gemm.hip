@@ -520,7 +520,8 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3 leaf products of 64x64 tiles, one workgroup per quad of output tiles
+// Split-bf16 leaf products of 64x64 tiles (BF16x3, and BF16x6 for tables past
+// the one-launch front), one workgroup per quad of output tiles
 // (2i+di, 2j+dj), eight waves: waves 2t and 2t+1 own rows 0-31 and 32-63 of
 // tile t = 2di+dj (2x4 blocks of 16x16 each), so four waves per SIMD fit and
 // the staging of a stage is spread over 512 threads (one A chunk and one B
@@ -530,10 +531,11 @@ __global__ __launch_bounds__((B == 64 ? 256 : 64)) void k_leaf_gemm_bf3(const Jo
 // of each row half and B_kj of each column half that some tile of the mask
 // needs, once for the quad, and each wave whose tile retains k multiplies.
 // Every tile sees its own retained k in increasing order with the MFMA
-// sequence of the one-tile kernel k_leaf_gemm_bf3 (four waves of 32x32
-// quadrants), and its norm and Newton-Schulz partials are summed over the
-// same quadrants in the same order, so a quad's tiles come out bitwise as
-// that kernel computes them at b = 64.
+// sequence (and, for BF16x6, the FP64 sum of the 32-k stage sums) of the
+// one-tile kernel k_leaf_gemm_bf3 (four waves of 32x32 quadrants), and its
+// norm and Newton-Schulz partials are summed over the same quadrants in the
+// same order, so a quad's tiles come out bitwise as that kernel computes them
+// at b = 64.
 // A stage holds 32 k.  A planes are rows of 32 bf16 (64 B) whose 16-byte
 // chunks are XOR-swizzled by (row/4) mod 4, so the 16 rows of a fragment read
 // fall in distinct banks; B planes (columns of k, transposed) keep the padded
@@ -556,13 +558,15 @@ __device__ inline int swz_a(int row, int k) {  // bf16 offset of (row, k) in an 
     return row * Bf3Quad::LDA + ((((k >> 3) ^ (row >> 2)) & 3) << 3) + (k & 7);
 }
 
-// At most 128 registers per lane, so that two workgroups (four waves per SIMD) share a CU.
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_leaf_gemm_bf3_quad(
-    const Job *__restrict__ jobs, const int32_t *__restrict__ work_count) {
+// NP = 2 (BF16x3): at most 128 registers per lane, so that two workgroups
+// (four waves per SIMD) share a CU.  NP = 3 (BF16x6): the three planes take
+// 110 KB of LDS, one workgroup per CU, up to 256 registers.
+template <int NP>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NP == 2 ? 4 : 2, NP == 2 ? 4 : 2))) void
+k_leaf_gemm_bf3_quad(const Job *__restrict__ jobs, const int32_t *__restrict__ work_count) {
     using C = Bf3Quad;
     constexpr int B = C::B;
     constexpr int NT = C::NT;
-    constexpr int NP = 2;
     __shared__ __attribute__((aligned(16))) __bf16 As[2][2][NP][B * C::LDA];
     __shared__ __attribute__((aligned(16))) __bf16 Bt[2][2][NP][B * C::LDB];
     __shared__ unsigned umask[QUAD_NB_MAX / 4];
@@ -623,13 +627,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const int ub = tid & 255;         // its (k pair, 4 columns) unit of that half
     const int kp = ub % (C::KS / 2), cg = ub / (C::KS / 2);
 
+    // NP = 3: each stage's six terms summed in FP32 from zero, the stage sums in
+    // FP64, as in k_leaf_gemm_bf3<64, 3>
+    constexpr bool ACC64 = NP == 3;
     v4f acc[2][4];
+    double acc64[ACC64 ? 2 : 1][ACC64 ? 4 : 1][4];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0.0f;
+    if constexpr (ACC64) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc64[bi][bj][r] = 0.0;
+    }
 
     auto needA = [](unsigned m, int h) { return (m & (h ? 0xcu : 0x3u)) != 0u; };
     auto needB = [](unsigned m, int h) { return (m & (h ? 0xau : 0x5u)) != 0u; };
@@ -695,7 +711,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 #pragma unroll
             for (int x = 0; x < NP; ++x) bf[x] = *(const bf16x8 *)&Bt[buf][dj][x][col * C::LDB + ko];
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi) acc[bi][bj] = mma_split<NP>(af[bi], bf, acc[bi][bj]);
+            for (int bi = 0; bi < 2; ++bi) {
+                if constexpr (ACC64) {
+                    const v4f t = mma_split<NP>(af[bi], bf, v4f{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[bi][bj][r] += (double)t[r];
+                } else {
+                    acc[bi][bj] = mma_split<NP>(af[bi], bf, acc[bi][bj]);
+                }
+            }
         }
     };
 
@@ -735,7 +759,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                     for (int r = 0; r < 4; ++r) {
                         const int row = rh * 32 + bi * 16 + 4 * (lane >> 4) + r;
                         const int col = wc * 32 + bj * 16 + (lane & 15);
-                        const double x = (double)acc[bi][2 * wc + bj][r];
+                        double x;
+                        if constexpr (ACC64)
+                            x = acc64[bi][2 * wc + bj][r];
+                        else
+                            x = (double)acc[bi][2 * wc + bj][r];
                         float out;
                         if (nsx) {
                             const int64_t gi = (int64_t)J.i * B + row, gj = (int64_t)J.j * B + col;
@@ -800,8 +828,8 @@ hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t s
     if (prec == P_F64) {
         gemm_dispatch_b<double>(leaf, t, st);
     } else if (prec == P_BF16X3) {
-        if (quad_tiles(prec, leaf))  // leaf 64
-            hipLaunchKernelGGL(k_leaf_gemm_bf3_quad, dim3(t.total_quads), dim3(Bf3Quad::NT), 0, st, t.jobs,
+        if (quad_tiles(prec, leaf, t.total_tiles))  // leaf 64
+            hipLaunchKernelGGL(k_leaf_gemm_bf3_quad<2>, dim3(t.total_quads), dim3(Bf3Quad::NT), 0, st, t.jobs,
                                t.work_count);
         else if (leaf == 32)
             hipLaunchKernelGGL((k_leaf_gemm_bf3<32, 2>), dim3(t.total_tiles), dim3(64), 0, st, t.jobs,
@@ -809,7 +837,10 @@ hipError_t launch_gemm_tab(int prec, int leaf, const ProdTable &t, hipStream_t s
         else
             return hipErrorInvalidValue;
     } else if (prec == P_BF16X6) {
-        if (leaf == 64)
+        if (quad_tiles(prec, leaf, t.total_tiles))
+            hipLaunchKernelGGL(k_leaf_gemm_bf3_quad<3>, dim3(t.total_quads), dim3(Bf3Quad::NT), 0, st, t.jobs,
+                               t.work_count);
+        else if (leaf == 64)
             hipLaunchKernelGGL((k_leaf_gemm_bf3<64, 3>), dim3(t.total_tiles), dim3(256), 0, st, t.jobs,
                                t.work_count);
         else if (leaf == 32)
