@@ -171,7 +171,7 @@ def test_continuous_batching_join_and_leave(ctx):
         np.testing.assert_array_equal(Z, Zs)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6"])
 def test_batched_reduced_precision_matches_solo(ctx, prec):
     mats = [inputs.kms(256, 0.7), inputs.gauss_gramian(6, 1.2), inputs.kms(640, 0.6)]
     solos = [solo(ctx, s, 64, 1e-6, prec=prec) for s in mats]
@@ -183,6 +183,25 @@ def test_batched_reduced_precision_matches_solo(ctx, prec):
         np.testing.assert_array_equal(host(Y), Ys)
         w, V = np.linalg.eigh(s)
         assert rel(host(Y), (V * np.sqrt(w)) @ V.T) < 1e-3
+
+
+def test_bf16x6_quads_in_a_shared_table_match_one_tile_solo(ctx):
+    """BF16x6 products of tables past 1024 tiles run on the quad kernel,
+    smaller tables one tile per workgroup, and the two give bitwise the same
+    tiles: three solves of 576-625 tiles each (alone: one tile per
+    workgroup) stepped together (1826 tiles: quads, the last quad row and
+    column of each product past its edge) must match their solo runs bit for
+    bit."""
+    mats = [inputs.kms(1600, 0.8), inputs.gauss_gramian(12, 1.0, n=1600), inputs.kms(1500, 0.6)]
+    solos = [solo(ctx, s, 64, 1e-8, prec="bf16x6") for s in mats]
+    solves = [ctx.solve_begin(dev(s), 1e-8, 1e-10, 30, leaf=64, prec="bf16x6", stagnation_stop=True) for s in mats]
+    while ctx.solve_step(solves, 4) > 0:
+        pass
+    for sv, (Ys, Zs, infos) in zip(solves, solos):
+        Y, Z, info = sv.finish()
+        assert info["status"] == infos["status"] and info["iterations"] == infos["iterations"]
+        np.testing.assert_array_equal(host(Y), Ys)
+        np.testing.assert_array_equal(host(Z), Zs)
 
 
 def test_footprint_and_errors(ctx):

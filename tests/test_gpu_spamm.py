@@ -170,7 +170,7 @@ def test_multiply_capacity_error(ctx):
     assert e.value.status == spamm.ECAPACITY
 
 
-@pytest.mark.parametrize("n,leaf", [(500, 32), (640, 64), (1630, 64)])
+@pytest.mark.parametrize("n,leaf", [(500, 32), (640, 64), (1630, 64), (2100, 64)])
 def test_multiply_bf16x6_error_vs_oracle(ctx, n, leaf):
     """One BF16x6 product (FP32 operands split into three bf16 pieces, six
     products, FP64 sums of the 32-k slices) against the oracle's FP64
