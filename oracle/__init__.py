@@ -63,6 +63,8 @@ def _load():
                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                                ctypes.c_int, ctypes.c_int, ip, ip]
             lib.oracle_product_rep.restype = ctypes.c_int
+            lib.oracle_damping.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+            lib.oracle_damping.restype = None
             for f in (lib.oracle_norms, lib.oracle_spamm, lib.oracle_spamm_tiles, lib.oracle_ns_sqrt,
                       lib.oracle_ns_step, lib.oracle_ns_single_step):
                 f.restype = ctypes.c_int
@@ -172,6 +174,14 @@ def ns_sqrt(s, leaf: int, tau: float, tol: float, maxit: int, tau_s: float = -1.
     k = it.value
     return dict(status=st, Y=Y, Z=Z, iterations=k, scale=sc.value, r=r[:k + 1].copy(), t=t[:k + 1].copy(),
                 nR=nr[:k + 1].copy())
+
+
+def damping(t: float, damped: bool = True) -> tuple[float, float]:
+    """(alpha, eps) of the map at relative trace error t (Sec. 4.2), as the
+    damped iteration uses them."""
+    a, e = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _load().oracle_damping(int(bool(damped)), float(t), ctypes.byref(a), ctypes.byref(e))
+    return a.value, e.value
 
 
 def ns_step(y, z, leaf: int, tau: float, tau_s: float = -1.0):

@@ -403,6 +403,9 @@ static void damping(int damped, double t, double *alpha, double *eps) {
     }
 }
 
+/* The damping at trace error t, exported so that tests can pin its constants. */
+void oracle_damping(int damped, double t, double *alpha, double *eps) { damping(damped, t, alpha, eps); }
+
 /* One dual-channel update (Sec. 3.2, eq. "cannonical"): x holds
  * x_k = y_k (x)_tau z_k on entry and h_k on exit, then
  * yn = h_k (x)_{tau_s} y_k, zn = z_k (x)_tau h_k.

@@ -457,6 +457,48 @@ def test_ns_status_codes():
 # off once t_k < 0.1
 # ---------------------------------------------------------------------------
 
+def test_damping_midpoints_and_sum_rule():
+    """Each sigmoid of Sec. 4.2 is halfway at its centre, and
+    sigma(c + d) + sigma(c - d) = 1 around it: alpha(0.35) = 1 + 1.85/2,
+    alpha(0.35 + d) + alpha(0.35 - d) = 2 + 1.85, eps(0.30) = 0.1/2 and
+    eps(0.30 + d) + eps(0.30 - d) = 0.1.  A wrong centre or amplitude fails
+    here whatever the slopes."""
+    a, e = oracle.damping(0.35)
+    assert abs(a - 1.925) <= 1e-15
+    a, e = oracle.damping(0.30)
+    assert abs(e - 0.05) <= 1e-16
+    for d in (0.05, 0.13, 0.19):  # both sides at t >= 0.1, where the sigmoids act
+        ap, ep = oracle.damping(0.35 + d)
+        am, _ = oracle.damping(0.35 - d)
+        assert abs(ap + am - 3.85) <= 1e-14
+        _, ep = oracle.damping(0.30 + d)
+        _, em = oracle.damping(0.30 - d)
+        assert abs(ep + em - 0.1) <= 1e-15
+
+
+def test_damping_slopes_and_limits():
+    """Slopes at the centres are amplitude x rate / 4 (1.85 x 50 / 4 and
+    0.1 x 75 / 4), and far above them alpha -> 2.85, eps -> 0.1."""
+    h = 1e-6
+    sa = (oracle.damping(0.35 + h)[0] - oracle.damping(0.35 - h)[0]) / (2 * h)
+    se = (oracle.damping(0.30 + h)[1] - oracle.damping(0.30 - h)[1]) / (2 * h)
+    assert abs(sa - 1.85 * 50 / 4) <= 1e-6 * 23.125
+    assert abs(se - 0.1 * 75 / 4) <= 1e-6 * 1.875
+    a, e = oracle.damping(1.0)
+    assert abs(a - 2.85) <= 1e-13 and abs(e - 0.1) <= 1e-15
+
+
+def test_damping_reading_switches_off_below_one_tenth():
+    """Reading of the paper's damping towards convergence: alpha = 1 and
+    eps = 0 exactly below t = 0.1 (and without damping), where the sigmoids
+    are already within 7e-6 and 3.1e-8 of those values."""
+    for t in (0.0, 0.05, 0.0999999):
+        assert oracle.damping(t) == (1.0, 0.0)
+    assert oracle.damping(0.6, damped=False) == (1.0, 0.0)
+    a, e = oracle.damping(0.1)
+    assert 0.0 < a - 1.0 < 7e-6 and 0.0 < e < 3.1e-8
+
+
 def test_damped_map_switched_off_equals_plain_map():
     """s' close to I (t_0 < 0.1 throughout): the damped run must be the plain
     run bit for bit (the switched-off map is the plain map)."""
