@@ -738,7 +738,7 @@ def run_copy(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
+        print(json.dumps({"error": "bench.py runs on one GPU; sharding across GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "batched":
