@@ -46,7 +46,8 @@ class Request:
     stagnation_stop: bool = True
     damped: bool = False
     single: bool = False
-    verify: bool = False            # also return the exact ||I - Y Z||_F (a dense product) as info["resid_exact"]
+    verify: bool = False            # also return the exact ||I - Y Z||_F (a dense product) as info["resid_exact"];
+                                    # the product's workspace stays with the lane's context, outside the budget
     t_submit: float = 0.0
     future: Future = field(default_factory=Future)
     footprint: int = 0
