@@ -93,6 +93,9 @@ def parse():
     p.add_argument("--nmax", type=int, default=16384, help="serving: largest n (log-uniform from 512)")
     p.add_argument("--iters-per-step", default="4", help="batched: iterations per synchronisation; serving: "
                    "one value or one per lane, comma-separated")
+    p.add_argument("--check", choices=("replay", "server"), default="replay",
+                   help="serving: exact residuals from the one-at-a-time replay (outside both timings), or "
+                        "computed by the server for every answer (inside the served time; no replay)")
     p.add_argument("--count-below", type=float, default=1e-2,
                    help="batched, serving: solves/s counts solves whose exact ||I - YZ||_F is at most this")
     p.add_argument("--pool-share", type=float, default=0.2,
@@ -257,7 +260,9 @@ def run_serving(args):
     the same either way (checked by checksums of every answer), so both run
     at the same accuracy.  The replay also computes each answer's exact
     ||I - Y Z||_F (a dense product, outside both timings), and solves/s counts
-    the answers at or below --count-below."""
+    the answers at or below --count-below.  With --check server the server
+    computes every answer's exact residual itself, inside the served time,
+    and no replay runs."""
     import threading
 
     import torch
@@ -273,6 +278,7 @@ def run_serving(args):
     # warm up kernels and tables on a tiny stream
     for f in [srv.submit(inputs.kms_device(n, 0.7, dev), 1e-6, 1e-8, leaf=64) for n in (512, 1024)]:
         f.result()
+    in_server = args.check == "server"
     futures = [None] * len(reqs)
     sums = [None] * len(reqs)
     done = [0]
@@ -307,7 +313,7 @@ def run_serving(args):
                     break
                 time.sleep(0.0005)
             s = inputs.build_spec_device(r, dev)
-            f = srv.submit(s, r["tau"], 1e-8, tau_s=0.01 * r["tau"], **opts)
+            f = srv.submit(s, r["tau"], 1e-8, tau_s=0.01 * r["tau"], verify=in_server, **opts)
             f.add_done_callback(make_cb(i))
             futures[i] = f
             del s
@@ -346,33 +352,37 @@ def run_serving(args):
     # ||I - Y Z||_F (a dense product) and its checksum: every answer is
     # bitwise the one served (equal checksums), so these residuals are the
     # served answers' residuals.
-    ctx = spamm.Context(0)
     ex1, sums1, service = [None] * len(reqs), [None] * len(reqs), []
-    for k, r in enumerate(reqs):
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        s = inputs.build_spec_device(r, dev)
-        Y, Z, info = ctx.ns_sqrt(s, r["tau"], 1e-8, tau_s=0.01 * r["tau"], raise_on_error=False, **opts)
-        torch.cuda.synchronize()
-        service.append(time.perf_counter() - ts)
-        if info["status"] >= 0:
-            ex1[k] = serve.exact_residual(ctx, Y, Z)
-            sums1[k] = (float(Y.sum()), float(Z.sum()))
-        del s, Y, Z
-        if len(service) % 200 == 0 or len(service) == len(reqs):
-            print(f"one at a time: {len(service)}/{len(reqs)}, busy {sum(service):.1f} s", file=sys.stderr,
-                  flush=True)
-    ctx.close()
-    t_free, lat1 = 0.0, []
-    for r, sv in zip(reqs, service):
-        start = max(r["t"], t_free)
-        t_free = start + sv
-        lat1.append(t_free - r["t"])
+    if not in_server:
+        ctx = spamm.Context(0)
+        for k, r in enumerate(reqs):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            s = inputs.build_spec_device(r, dev)
+            Y, Z, info = ctx.ns_sqrt(s, r["tau"], 1e-8, tau_s=0.01 * r["tau"], raise_on_error=False, **opts)
+            torch.cuda.synchronize()
+            service.append(time.perf_counter() - ts)
+            if info["status"] >= 0:
+                ex1[k] = serve.exact_residual(ctx, Y, Z)
+                sums1[k] = (float(Y.sum()), float(Z.sum()))
+            del s, Y, Z
+            if len(service) % 200 == 0 or len(service) == len(reqs):
+                print(f"one at a time: {len(service)}/{len(reqs)}, busy {sum(service):.1f} s", file=sys.stderr,
+                      flush=True)
+        ctx.close()
+        t_free, lat1 = 0.0, []
+        for r, sv in zip(reqs, service):
+            start = max(r["t"], t_free)
+            t_free = start + sv
+            lat1.append(t_free - r["t"])
 
     # counted: answered solves whose exact ||I - Y Z||_F is at most
     # --count-below; diverged ones (status < 0) are answered but never counted
-    ex = [ex1[i] for _, _, i in results]
-    same = all(sums1[i] == sums[i] for res, _, i in results if res.info["status"] >= 0)
+    if in_server:
+        ex = [res.info.get("resid_exact") for res, _, _ in results]
+    else:
+        ex = [ex1[i] for _, _, i in results]
+        same = all(sums1[i] == sums[i] for res, _, i in results if res.info["status"] >= 0)
     counted = [e is not None and e <= args.count_below for e in ex]
     nvalid = sum(counted)
     div_by = {}
@@ -393,10 +403,11 @@ def run_serving(args):
         accuracy[f"tau={tau:g}"] = {"answered_status_ge0": len(rex), "resid_exact": pct(rex),
                                     "resid_inloop": pct(rin),
                                     "at_or_below": {f"{x:g}": sum(1 for e in rex if e <= x) for x in thresholds}}
-    one = {"solves_per_s": nvalid / t_free, "makespan_s": t_free, "busy_s": float(sum(service)),
-           "capacity_solves_per_s": nvalid / float(sum(service)),
-           "p50_latency_s": float(np.percentile(lat1, 50)), "p99_latency_s": float(np.percentile(lat1, 99)),
-           "mean_latency_s": float(np.mean(lat1)), "same_answers_as_served": same}
+    one = None if in_server else {
+        "solves_per_s": nvalid / t_free, "makespan_s": t_free, "busy_s": float(sum(service)),
+        "capacity_solves_per_s": nvalid / float(sum(service)),
+        "p50_latency_s": float(np.percentile(lat1, 50)), "p99_latency_s": float(np.percentile(lat1, 99)),
+        "mean_latency_s": float(np.mean(lat1)), "same_answers_as_served": same}
     line = {
         "metric": "NS sqrt serving: solves/sec and p50/p99 latency under Poisson arrivals",
         "value": nvalid / t_end, "unit": "solves/s", "n_gpus": 1, "steps": len(results), "warmup": 2,
@@ -418,7 +429,9 @@ def run_serving(args):
             "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
             "accuracy_by_tau": accuracy,
             "one_at_a_time": one,
-            "speedup_vs_one_at_a_time": one["makespan_s"] / t_end,
+            "residuals_from": ("the server, for every answer (inside the served time)" if in_server else
+                               "the one-at-a-time replay, checksum-equal answers (outside both timings)"),
+            "speedup_vs_one_at_a_time": one["makespan_s"] / t_end if one else None,
             "useful_tflops": sum(res.info["flops_total"] for res, _, _ in results) / t_end / 1e12,
             "engine": stats,
         },
