@@ -38,7 +38,8 @@
  * Parity pins: every function here is checked in the CPU test suite against
  * something other than itself (NumPy norms and products, brute-force culling,
  * the Proposition's bound, eigendecomposition, the KMS closed-form inverse,
- * Higham's sign identity, the scalar spectral recurrence).
+ * Higham's sign identity, the scalar spectral recurrence, and the centres,
+ * symmetry, slopes and limits of the damping sigmoids).
  *
  * Parity unpinned: the trajectory of the iteration at tau > 0 (its residual
  * and retained counts step by step) has no printed values in the paper; it is
