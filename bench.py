@@ -249,6 +249,38 @@ def batched_cpu_baseline(specs, leaves, infos, counted, tol, maxit, tsr, budget_
                        f"{counted} counted solves")}
 
 
+def serving_cpu_baseline(reqs, results, counted, t_end, budget_s=20.0):
+    """The oracle (FP64 leaves, the same options) on a sample of the served
+    requests: every 25th by size, smallest first, until about budget_s of
+    CPU time.  Its flop rate on the sample scales the stream's retained leaf
+    products (the served run's) to an estimated one-at-a-time CPU time."""
+    import oracle
+
+    from paper_1508_05856_amd import inputs
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i]["n"])
+    secs, flops, used = 0.0, 0.0, []
+    for i in order[::25]:
+        if secs > budget_s:
+            break
+        r = reqs[i]
+        a = inputs.build_spec(r)
+        t0 = time.perf_counter()
+        o = oracle.ns_sqrt(a, 64, r["tau"], 1e-8, 40, tau_s=0.01 * r["tau"], stagnation_stop=True)
+        secs += time.perf_counter() - t0
+        flops += 2.0 * 64 ** 3 * float(o["nR"].sum())
+        used.append(r["n"])
+    rate = flops / secs
+    total = float(sum(res.info["flops_total"] for res, _, _ in results))
+    est = total / rate
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": counted / est, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"the oracle's whole solves of {len(used)} of the {len(reqs)} requests (n = "
+                       f"{', '.join(map(str, used))}): {secs:.1f} s at {rate / 1e9:.2f} GFLOP/s of retained leaf "
+                       f"products; the stream's {total / 1e12:.1f} TFLOP at that rate take {est:.0f} s for its "
+                       f"{counted} counted solves (the GPU served them in {t_end:.0f} s); the sample holds the "
+                       f"smallest requests, on which the oracle's rate may be lower than on the large ones")}
+
+
 def run_serving(args):
     """Poisson arrivals of sqrt / inverse-sqrt requests (n log-uniform in
     [512, nmax], KMS and Gaussian, tau in {1e-4, 1e-6, 1e-8}, tol 1e-8, FP64)
@@ -435,6 +467,7 @@ def run_serving(args):
             "useful_tflops": sum(res.info["flops_total"] for res, _, _ in results) / t_end / 1e12,
             "engine": stats,
         },
+        "cpu_baseline": None if args.no_cpu_baseline else serving_cpu_baseline(reqs, results, nvalid, t_end),
     }
     print(json.dumps(line), flush=True)
 
