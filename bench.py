@@ -67,8 +67,10 @@ def committed_traffic(workload: str, prec: str):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
-    p.add_argument("--warmup", type=int, default=1)
+    # c3: a step is one iteration and a whole n = 32768 solve takes 14, so
+    # the default region holds one whole solve
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--tau", type=float, default=None)
     p.add_argument("--tau-s", type=float, default=-1.0)
     p.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3", "bf16x6"])
