@@ -619,6 +619,8 @@ def run_c3(args):
         info = None
         sec_per_solve = None
         how = None
+        print(f"no solve ran whole inside the {args.steps} timed iterations: value needs --steps at least "
+              f"the iterations of one solve (14 at n = 32768)", file=sys.stderr, flush=True)
 
     useful = flops / (float(np.sum(gemm_ms)) * 1e-3) / 1e12
     achieved = EXEC_PER_USEFUL[args.prec] * useful
