@@ -108,3 +108,20 @@ def test_single_channel_bf16x6_error(ctx, leaf):
     ey, ez = rel(Y.cpu().numpy(), o["Y"]), rel(Z.cpu().numpy(), o["Z"])
     print(f"single bf16x6 leaf {leaf}: relY {ey:.2e} relZ {ez:.2e}")
     assert ey <= 5e-6 and ez <= 5e-6
+
+
+def test_single_channel_bf16x6_quads_error():
+    """A single-channel solve whose tables pass 1024 tiles (n = 2100, 33 x 33
+    tiles of 64, the last quad row and column past the edge), so the BF16x6
+    products, the transposed z^T included, run on the quad kernel: Y and Z
+    within 5e-6 of the FP64 oracle on the KMS matrix (kappa 32)."""
+    from paper_1508_05856_amd import spamm
+    ctx = spamm.Context(0)
+    s = inputs.kms(2100, 0.7)
+    Y, Z, info = ctx.ns_sqrt(dev(s), 1e-8, 1e-5, 40, leaf=64, prec="bf16x6", stagnation_stop=True, single=True)
+    ctx.close()
+    o = oracle.ns_sqrt(s, 64, 1e-8, 1e-5, 40, stagnation_stop=True, single=True)
+    ey, ez = rel(Y.cpu().numpy(), o["Y"]), rel(Z.cpu().numpy(), o["Z"])
+    print(f"single bf16x6 quads n=2100: relY {ey:.2e} relZ {ez:.2e}; updates {info['iterations']} vs {o['iterations']}")
+    assert info["status"] == o["status"]
+    assert ey <= 5e-6 and ez <= 5e-6
