@@ -767,8 +767,12 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
         if (!fuse) TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
         TRY(enqueue_front(ctx, p->tz, p->leaf, gemm_prec(p->prec), st));
         TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tz, st));
-        TIMED(K_PYR, launch_pyramid_tab(p->tz, st));
-        HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
+        if (decide_builds_pyramid(p->tz)) {
+            TIMED(K_PYR, launch_pyramid_advance(p->solves, p->nsolve, p->tz, 1, st));
+        } else {
+            TIMED(K_PYR, launch_pyramid_tab(p->tz, st));
+            HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
+        }
         return SPAMM_OK;
     }
     TRY(enqueue_front(ctx, p->tx, p->leaf, gemm_prec(p->prec), st));
@@ -779,8 +783,12 @@ int enqueue_iteration(spamm_ctx *ctx, Plan *p, hipStream_t st) {
     if (!fuse) TIMED(K_PYR, launch_pyramid_tab(p->tx, st));
     TRY(enqueue_front(ctx, p->tyz, p->leaf, gemm_prec(p->prec), st));
     TIMED(K_GEMM, launch_gemm_tab(gemm_prec(p->prec), p->leaf, p->tyz, st));
-    TIMED(K_PYR, launch_pyramid_tab(p->tyz, st));
-    HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
+    if (decide_builds_pyramid(p->tyz)) {
+        TIMED(K_PYR, launch_pyramid_advance(p->solves, p->nsolve, p->tyz, 2, st));
+    } else {
+        TIMED(K_PYR, launch_pyramid_tab(p->tyz, st));
+        HIPCHK(launch_ns_advance(p->solves, p->nsolve, st));
+    }
     return SPAMM_OK;
 }
 

@@ -206,6 +206,11 @@ hipError_t launch_transpose_tab(int prec, const ProdTable &t, int leaf, hipStrea
 hipError_t launch_ns_map(int prec, const ProdTable &t, int leaf, hipStream_t st);
 // After a (y, z) update: parity ^= 1, k += 1 for running solves.
 hipError_t launch_ns_advance(const SolveDesc *solves, int nsolve, hipStream_t st);
+// The pyramids of the update products of table t (per products per solve, in
+// the solves' order), then the advance, in one launch; valid when
+// decide_builds_pyramid(t) holds (every P <= 32).
+hipError_t launch_pyramid_advance(const SolveDesc *solves, int nsolve, const ProdTable &t, int per,
+                                  hipStream_t st);
 // Copy each solve's state into a contiguous array (for one read-back).
 hipError_t launch_gather_states(const SolveDesc *solves, int nsolve, SolveState *out, hipStream_t st);
 

@@ -1093,6 +1093,28 @@ __global__ __launch_bounds__(64) void k_ns_advance(const SolveDesc *__restrict__
     st->k += 1;
 }
 
+// The update products' pyramids built by the block of their solve, which
+// then advances it: one launch in place of k_pyramid_tab1 and k_ns_advance,
+// for tables whose every pyramid is one region (P <= 32).  Products
+// per*s .. per*s+per-1 of the table belong to solve s.
+__global__ __launch_bounds__(256) void k_pyramid_advance(const SolveDesc *__restrict__ solves,
+                                                         const ProdDesc *__restrict__ prods, int per) {
+    __shared__ double buf[32 * 32];
+    const int s = blockIdx.x;
+    SolveState *st = solves[s].state;
+    if (st->status != ST_RUNNING) return;  // the same for every thread of the block
+    for (int q = 0; q < per; ++q) {
+        const ProdDesc &d = prods[s * per + q];
+        const int par = prod_parity(d);
+        pyramid_region(d.qC[par], d.nrmC[par], d.P, d.P, d.nb, 1, 0, buf);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {  // every thread has read the parity
+        st->parity ^= 1;
+        st->k += 1;
+    }
+}
+
 __global__ __launch_bounds__(64) void k_gather_states(const SolveDesc *__restrict__ solves, int nsolve,
                                                       SolveState *__restrict__ out) {
     const int i = blockIdx.x * 64 + threadIdx.x;
@@ -1108,6 +1130,12 @@ bool decide_builds_pyramid(const ProdTable &tx) { return tx.total_pyr == tx.npro
 
 hipError_t launch_ns_advance(const SolveDesc *solves, int nsolve, hipStream_t st) {
     hipLaunchKernelGGL(k_ns_advance, dim3((nsolve + 63) / 64), dim3(64), 0, st, solves, nsolve);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramid_advance(const SolveDesc *solves, int nsolve, const ProdTable &t, int per,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(k_pyramid_advance, dim3(nsolve), dim3(256), 0, st, solves, t.prods, per);
     return hipGetLastError();
 }
 
