@@ -364,7 +364,7 @@ TableSizes table_sizes(const ProdDesc *prods, int nprod) {
     TableSizes z{nprod, 0, 0, 0, 0, 0, 0, 0};
     for (int p = 0; p < nprod; ++p) {
         const ProdDesc &d = prods[p];
-        z.total_cull += (d.nb * d.nb + 3) / 4;
+        z.total_cull += cull_blocks(d.nb);
         z.total_tiles += d.nb * d.nb;
         z.total_quads += ((d.nb + 1) / 2) * ((d.nb + 1) / 2);
         z.total_pyr += d.P <= 32 ? 1 : (d.P / 32) * (d.P / 32);
@@ -415,7 +415,7 @@ ProdTable layout_table(Carve &c, const ProdDesc *prods, int nprod, std::vector<c
         cull[0] = tile[0] = pyr[0] = pyr2[0] = 0;
         for (int p = 0; p < z.nprod; ++p) {
             const ProdDesc &d = prods[p];
-            cull[p + 1] = cull[p] + (d.nb * d.nb + 3) / 4;
+            cull[p + 1] = cull[p] + cull_blocks(d.nb);
             tile[p + 1] = tile[p] + d.nb * d.nb;
             pyr[p + 1] = pyr[p] + (d.P <= 32 ? 1 : (d.P / 32) * (d.P / 32));
             pyr2[p + 1] = pyr2[p] + (d.P > 32 ? 1 : 0);

@@ -122,12 +122,21 @@ struct Job {
     int k0, k1;           // list[0], list[1] when present (the first stages need no list load)
 };
 
+// The cull runs one wave per block of CULL_RI x CULL_J output tiles of a
+// product (CULL_RI rows of tiles, CULL_J columns); cull_blocks(nb) is its
+// count of four-wave workgroups.
+constexpr int CULL_RI = 4, CULL_J = 16;
+__host__ __device__ inline int cull_waves(int nb) {
+    return ((nb + CULL_RI - 1) / CULL_RI) * ((nb + CULL_J - 1) / CULL_J);
+}
+__host__ __device__ inline int cull_blocks(int nb) { return (cull_waves(nb) + 3) / 4; }
+
 // Device-side tables of one set of products, built on the host when the set
 // changes and then reused by every launch over that set.
 struct ProdTable {
     const ProdDesc *prods;    // device array
     int nprod;
-    const int32_t *cull_pre;  // nprod+1 prefix of cull blocks (ceil(nb*nb/4) per product)
+    const int32_t *cull_pre;  // nprod+1 prefix of cull blocks (cull_blocks(nb) per product)
     const int32_t *tile_pre;  // nprod+1 prefix of nb*nb tiles
     const int32_t *pyr_pre;   // nprod+1 prefix of first-pass pyramid regions
     const int32_t *pyr2_pre;  // nprod+1 prefix of second-pass pyramid blocks (1 per product with P > 32)

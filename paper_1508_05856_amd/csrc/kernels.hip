@@ -70,7 +70,7 @@ __global__ __launch_bounds__(1024) void k_table_one(ProdDesc d, ProdTable t) {
         int32_t *cull = const_cast<int32_t *>(t.cull_pre), *tile = const_cast<int32_t *>(t.tile_pre);
         int32_t *pyr = const_cast<int32_t *>(t.pyr_pre), *pyr2 = const_cast<int32_t *>(t.pyr2_pre);
         cull[0] = tile[0] = pyr[0] = pyr2[0] = 0;
-        cull[1] = (nb2 + 3) / 4;
+        cull[1] = cull_blocks(nb);
         tile[1] = nb2;
         pyr[1] = P <= 32 ? 1 : (P / 32) * (P / 32);
         pyr2[1] = P > 32 ? 1 : 0;
@@ -436,10 +436,10 @@ hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st) {
 // thr = tau * (||A|| * ||B||), in increasing k.  Flat enumeration: since a
 // parent's squared norm is a sum of non-negative children, every ancestor
 // triple of a kept leaf triple is kept, so this equals the recursive set.
-// One wave per output tile: lane l tests k = kb + l, a ballot gives the kept
-// k of the group of 64 and each kept lane writes its k at its rank.  A row of
-// A's leaf norms and a column of B's (from the transposed copy) are read
-// coalesced.
+// One wave per block of CULL_RI x CULL_J output tiles; for each tile lane l
+// tests k = kb + l, a ballot gives the kept k of the group of 64 and each kept
+// lane writes its k at its rank.  Rows of A's leaf norms and columns of B's
+// (from the transposed copy) are read coalesced.
 // ---------------------------------------------------------------------------
 // Cull of tile t of a running product by one wave (lane = lane index);
 // returns the count, and the first two kept k in k0, k1 (-1 when absent).
@@ -477,17 +477,100 @@ __device__ inline int cull_tile(const ProdDesc &d, int t, int lane, int &k0, int
     return base;
 }
 
+template <typename T>
+using gptr = T __attribute__((address_space(1))) *;
+
+// Cull of the CULL_RI x CULL_J block of tiles (rows i0..i1-1, columns
+// j0..j1-1) by one wave, for nb <= 64 * CULL_U: the leaf norms of the block's
+// CULL_RI rows of A stay in registers and B's columns come CULL_JG at a time,
+// all their loads issued together, so a wave waits one memory round trip per
+// CULL_JG columns (rather than one per 64 k of every tile) and reads each of
+// A's rows once for CULL_J tiles.  Lists, counts and order are those of
+// cull_tile.
+constexpr int CULL_U = 8, CULL_JG = 4;
+__device__ inline void cull_block_regs(const ProdDesc &d, int i0, int i1, int j0, int j1, int lane) {
+    const int par = prod_parity(d);
+    const int nb = d.nb;
+    const double thr = d.tau * (sqrt(*d.rootA[par]) * sqrt(*d.rootB[par]));
+    const gptr<const double> nA = (gptr<const double>)d.nrmA[par];
+    const gptr<const double> nBt = (gptr<const double>)(d.nrmB[par] + (int64_t)nb * nb);  // ||B_kj|| at [j*nb + k]
+    const gptr<int32_t> kidx = (gptr<int32_t>)d.kidx;
+    const gptr<int32_t> cnt = (gptr<int32_t>)d.cnt;
+    double pa[CULL_RI][CULL_U];
+#pragma unroll
+    for (int r = 0; r < CULL_RI; ++r)
+#pragma unroll
+        for (int u = 0; u < CULL_U; ++u) {
+            const int k = 64 * u + lane;
+            pa[r][u] = (i0 + r < i1 && k < nb) ? nA[(int64_t)(i0 + r) * nb + k] : 0.0;
+        }
+    unsigned long long inb[CULL_U];  // lanes whose k = 64u + lane < nb
+#pragma unroll
+    for (int u = 0; u < CULL_U; ++u) inb[u] = __builtin_amdgcn_ballot_w64(64 * u + lane < nb);
+    for (int jg = j0; jg < j1; jg += CULL_JG) {
+        double b[CULL_JG][CULL_U];
+#pragma unroll
+        for (int c = 0; c < CULL_JG; ++c) {
+            const int j = min(jg + c, j1 - 1);  // past the block: a repeated column, not used
+#pragma unroll
+            for (int u = 0; u < CULL_U; ++u) {
+                const int k = 64 * u + lane;
+                b[c][u] = k < nb ? nBt[(int64_t)j * nb + k] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CULL_JG; ++c) {
+            const int j = jg + c;
+            if (j >= j1) break;  // wave-uniform
+#pragma unroll
+            for (int r = 0; r < CULL_RI; ++r) {
+                if (i0 + r >= i1) break;  // wave-uniform
+                const int t = __builtin_amdgcn_readfirstlane((i0 + r) * nb + j);
+                const gptr<int32_t> out = kidx + (int64_t)t * nb;
+                int base = 0;
+#pragma unroll
+                for (int u = 0; u < CULL_U; ++u) {
+                    if (64 * u >= nb) break;  // wave-uniform
+                    const int k = 64 * u + lane;
+                    const bool pass = !(pa[r][u] * b[c][u] < thr);
+                    const bool keep = k < nb && pass;
+                    // the ballot of the compare alone, masked by the lanes of k < nb
+                    const unsigned long long mask = __builtin_amdgcn_ballot_w64(pass) & inb[u];
+                    // rank of this lane among the kept lanes below it
+                    const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+                    if (keep) out[base + (int)rank] = k;
+                    base += __popcll(mask);
+                }
+                if (lane == 0) cnt[t] = base;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_cull_tab(const ProdDesc *__restrict__ prods,
                                                   const int32_t *__restrict__ pre, int nprod) {
     const int p = find_slot(pre, nprod, blockIdx.x);
     const ProdDesc &d = prods[p];
     if (!prod_running(d)) return;
-    const int t = (blockIdx.x - pre[p]) * 4 + (threadIdx.x >> 6);
-    if (t >= d.nb * d.nb) return;
+    const int nb = d.nb;
+    const int wv = (blockIdx.x - pre[p]) * 4 + (threadIdx.x >> 6);
+    if (wv >= cull_waves(nb)) return;  // whole waves
     const int lane = threadIdx.x & 63;
-    int k0, k1;
-    const int cnt = cull_tile(d, t, lane, k0, k1);
-    if (lane == 0) d.cnt[t] = cnt;
+    const int nbj = (nb + CULL_J - 1) / CULL_J;
+    const int i0 = (wv / nbj) * CULL_RI, j0 = (wv % nbj) * CULL_J;
+    const int i1 = min(i0 + CULL_RI, nb), j1 = min(j0 + CULL_J, nb);
+    if (nb <= 64 * CULL_U) {
+        cull_block_regs(d, i0, i1, j0, j1, lane);
+        return;
+    }
+    for (int i = i0; i < i1; ++i)
+        for (int j = j0; j < j1; ++j) {
+            int k0, k1;
+            const int t = i * nb + j;
+            const int c = cull_tile(d, t, lane, k0, k1);
+            if (lane == 0) d.cnt[t] = c;
+        }
 }
 
 hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st) {
