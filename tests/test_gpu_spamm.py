@@ -149,6 +149,40 @@ def test_multiply_large_tables_match_oracle(ctx, n):
         assert np.abs(g_ - o[:g_.shape[0], :g_.shape[1]]).max() <= 1e-13 * scale, (i, j)
 
 
+def banded(n, seed, rate, width):
+    """Exponential decay with random signs inside |i - j| <= width, zero outside."""
+    g = np.random.default_rng(seed)
+    a = np.zeros((n, n))
+    for d in range(-width, width + 1):
+        m = n - abs(d)
+        r = np.arange(max(0, -d), max(0, -d) + m)
+        a[r, r + d] = np.exp(-rate * abs(d)) * g.standard_normal(m)
+    return a
+
+
+@pytest.mark.parametrize("n", [8192, 8200])
+def test_multiply_cull_past_512_tiles_per_side_matches_oracle(ctx, n):
+    """Leaf 16 at nb = 512 (the cull's register-blocked path, every group of
+    64 k full) and nb = 513 (past it: the per-tile path, and a ragged last
+    tile of 8): the retained triple set equals the oracle's recursive cull
+    (near-ties excluded) and the product is within 1e-13 of ||A|| ||B||."""
+    leaf, tau = 16, 1e-7
+    a = banded(n, 21, 0.02, 480)
+    b = banded(n, 22, 0.02, 480)
+    C, stats, trip = ctx.spamm_multiply(dev(a), dev(b), tau, leaf, triples=True)
+    Co, Ro, cnt = oracle.spamm(a, b, leaf, tau)
+    nb = -(-n // leaf)
+    assert nb == (512 if n == 8192 else 513)
+    assert 0 < cnt < nb ** 3
+    diff = set(map(tuple, host(trip).tolist())) ^ set(map(tuple, Ro.tolist()))
+    if diff:  # only near-ties may differ
+        la, lb = oracle.norms(a, leaf), oracle.norms(b, leaf)
+        thr = tau * (la[-1][0, 0] * lb[-1][0, 0])
+        for (i, j, k) in diff:
+            assert abs(la[0][i, k] * lb[0][k, j] - thr) <= 1e-12 * thr, (i, j, k)
+    assert np.abs(host(C) - Co).max() <= 1e-13 * np.linalg.norm(a) * np.linalg.norm(b)
+
+
 def test_multiply_block_diagonal_and_limits(ctx):
     b, nb = 32, 8
     n = b * nb
