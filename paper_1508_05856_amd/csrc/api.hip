@@ -357,14 +357,15 @@ int validate_common(spamm_ctx *ctx, const void *A, int64_t n, int64_t ld, int le
 
 // ---- product tables ----------------------------------------------------------
 struct TableSizes {
-    int nprod, total_cull, total_tiles, total_pyr, total_pyr2, total_quads, max_nb, hist_blocks;
+    int nprod, total_cull, total_cullb, total_tiles, total_pyr, total_pyr2, total_quads, max_nb, hist_blocks;
 };
 
 TableSizes table_sizes(const ProdDesc *prods, int nprod) {
-    TableSizes z{nprod, 0, 0, 0, 0, 0, 0, 0};
+    TableSizes z{nprod, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int p = 0; p < nprod; ++p) {
         const ProdDesc &d = prods[p];
         z.total_cull += cull_blocks(d.nb);
+        z.total_cullb += cull_blk_blocks(d.nb);
         z.total_tiles += d.nb * d.nb;
         z.total_quads += ((d.nb + 1) / 2) * ((d.nb + 1) / 2);
         z.total_pyr += d.P <= 32 ? 1 : (d.P / 32) * (d.P / 32);
@@ -385,6 +386,8 @@ ProdTable layout_table(Carve &c, const ProdDesc *prods, int nprod, std::vector<c
     t.prods = c.take<ProdDesc>(z.nprod);
     const size_t o_cull = c.off;
     t.cull_pre = c.take<int32_t>(z.nprod + 1);
+    const size_t o_cullb = c.off;
+    t.cullb_pre = c.take<int32_t>(z.nprod + 1);
     const size_t o_tile = c.off;
     t.tile_pre = c.take<int32_t>(z.nprod + 1);
     const size_t o_pyr = c.off;
@@ -400,6 +403,7 @@ ProdTable layout_table(Carve &c, const ProdDesc *prods, int nprod, std::vector<c
     t.nprod = z.nprod;
     t.hist_blocks = z.hist_blocks;
     t.total_cull = z.total_cull;
+    t.total_cullb = z.total_cullb;
     t.total_tiles = z.total_tiles;
     t.total_quads = z.total_quads;
     t.total_pyr = z.total_pyr;
@@ -409,13 +413,14 @@ ProdTable layout_table(Carve &c, const ProdDesc *prods, int nprod, std::vector<c
         if (host->size() < c.off) host->resize(c.off);
         char *h = host->data();
         std::memcpy(h + o_prods, prods, (size_t)nprod * sizeof(ProdDesc));
-        int32_t *cull = (int32_t *)(h + o_cull), *tile = (int32_t *)(h + o_tile);
+        int32_t *cull = (int32_t *)(h + o_cull), *cullb = (int32_t *)(h + o_cullb), *tile = (int32_t *)(h + o_tile);
         int32_t *pyr = (int32_t *)(h + o_pyr), *pyr2 = (int32_t *)(h + o_pyr2);
         int32_t *mort = (int32_t *)(h + o_mort);
-        cull[0] = tile[0] = pyr[0] = pyr2[0] = 0;
+        cull[0] = cullb[0] = tile[0] = pyr[0] = pyr2[0] = 0;
         for (int p = 0; p < z.nprod; ++p) {
             const ProdDesc &d = prods[p];
             cull[p + 1] = cull[p] + cull_blocks(d.nb);
+            cullb[p + 1] = cullb[p] + cull_blk_blocks(d.nb);
             tile[p + 1] = tile[p] + d.nb * d.nb;
             pyr[p + 1] = pyr[p] + (d.P <= 32 ? 1 : (d.P / 32) * (d.P / 32));
             pyr2[p + 1] = pyr2[p] + (d.P > 32 ? 1 : 0);

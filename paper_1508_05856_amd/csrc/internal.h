@@ -122,21 +122,28 @@ struct Job {
     int k0, k1;           // list[0], list[1] when present (the first stages need no list load)
 };
 
-// The cull runs one wave per block of CULL_RI x CULL_J output tiles of a
-// product (CULL_RI rows of tiles, CULL_J columns); cull_blocks(nb) is its
-// count of four-wave workgroups.
-constexpr int CULL_RI = 4, CULL_J = 16;
-__host__ __device__ inline int cull_waves(int nb) {
+// The cull: products of fewer than CULL_BLOCK_NB tiles per side run one wave
+// per output tile (k_cull_tab: few registers, many waves in flight); larger
+// ones one wave per block of CULL_RI x CULL_J tiles (k_cull_blk), which keeps
+// the leaf norms of its rows of A in registers across the block (such a
+// product still has at least 1024 blocks).  Each kernel has its own prefix of
+// four-wave workgroups over the products of a table, zero for products of the
+// other kind.
+constexpr int CULL_RI = 4, CULL_J = 16, CULL_BLOCK_NB = 256;
+__host__ __device__ inline bool cull_blocked(int nb) { return nb >= CULL_BLOCK_NB; }
+__host__ __device__ inline int cull_blk_waves(int nb) {
     return ((nb + CULL_RI - 1) / CULL_RI) * ((nb + CULL_J - 1) / CULL_J);
 }
-__host__ __device__ inline int cull_blocks(int nb) { return (cull_waves(nb) + 3) / 4; }
+__host__ __device__ inline int cull_blocks(int nb) { return cull_blocked(nb) ? 0 : (nb * nb + 3) / 4; }
+__host__ __device__ inline int cull_blk_blocks(int nb) { return cull_blocked(nb) ? (cull_blk_waves(nb) + 3) / 4 : 0; }
 
 // Device-side tables of one set of products, built on the host when the set
 // changes and then reused by every launch over that set.
 struct ProdTable {
     const ProdDesc *prods;    // device array
     int nprod;
-    const int32_t *cull_pre;  // nprod+1 prefix of cull blocks (cull_blocks(nb) per product)
+    const int32_t *cull_pre;  // nprod+1 prefix of k_cull_tab blocks (cull_blocks(nb) per product)
+    const int32_t *cullb_pre; // nprod+1 prefix of k_cull_blk blocks (cull_blk_blocks(nb) per product)
     const int32_t *tile_pre;  // nprod+1 prefix of nb*nb tiles
     const int32_t *pyr_pre;   // nprod+1 prefix of first-pass pyramid regions
     const int32_t *pyr2_pre;  // nprod+1 prefix of second-pass pyramid blocks (1 per product with P > 32)
@@ -148,7 +155,7 @@ struct ProdTable {
     int32_t *work_count;      // device scalar: valid entries in `work` (tiles or quads)
     int32_t *hist;            // NBUCKET * hist_blocks scratch for the large-table sort
     int hist_blocks;
-    int total_cull, total_tiles, total_pyr, total_pyr2;
+    int total_cull, total_cullb, total_tiles, total_pyr, total_pyr2;
     int total_quads;          // sum of ceil(nb/2)^2
     int max_nb;
 };

@@ -67,10 +67,12 @@ __global__ __launch_bounds__(1024) void k_table_one(ProdDesc d, ProdTable t) {
     if (tid == 0) {
         *const_cast<ProdDesc *>(t.prods) = d;
         const int32_t nb2 = nb * nb;
-        int32_t *cull = const_cast<int32_t *>(t.cull_pre), *tile = const_cast<int32_t *>(t.tile_pre);
+        int32_t *cull = const_cast<int32_t *>(t.cull_pre), *cullb = const_cast<int32_t *>(t.cullb_pre);
+        int32_t *tile = const_cast<int32_t *>(t.tile_pre);
         int32_t *pyr = const_cast<int32_t *>(t.pyr_pre), *pyr2 = const_cast<int32_t *>(t.pyr2_pre);
-        cull[0] = tile[0] = pyr[0] = pyr2[0] = 0;
+        cull[0] = cullb[0] = tile[0] = pyr[0] = pyr2[0] = 0;
         cull[1] = cull_blocks(nb);
+        cullb[1] = cull_blk_blocks(nb);
         tile[1] = nb2;
         pyr[1] = P <= 32 ? 1 : (P / 32) * (P / 32);
         pyr2[1] = P > 32 ? 1 : 0;
@@ -436,13 +438,17 @@ hipError_t launch_pyramid_tab(const ProdTable &t, hipStream_t st) {
 // thr = tau * (||A|| * ||B||), in increasing k.  Flat enumeration: since a
 // parent's squared norm is a sum of non-negative children, every ancestor
 // triple of a kept leaf triple is kept, so this equals the recursive set.
-// One wave per block of CULL_RI x CULL_J output tiles; for each tile lane l
-// tests k = kb + l, a ballot gives the kept k of the group of 64 and each kept
-// lane writes its k at its rank.  Rows of A's leaf norms and columns of B's
+// One wave per output tile, or per block of CULL_RI x CULL_J tiles for large
+// products; for each tile lane l tests k = kb + l, a ballot gives the kept k
+// of the group of 64 and each kept lane writes its k at its rank.  Rows of A's leaf norms and columns of B's
 // (from the transposed copy) are read coalesced.
 // ---------------------------------------------------------------------------
 // Cull of tile t of a running product by one wave (lane = lane index);
 // returns the count, and the first two kept k in k0, k1 (-1 when absent).
+// The norms of CULL_TU groups of 64 k are loaded before any of their
+// compares and list stores, so a wave waits one round trip per 64*CULL_TU k
+// rather than one per group (the stores would order later loads behind them).
+constexpr int CULL_TU = 4;
 __device__ inline int cull_tile(const ProdDesc &d, int t, int lane, int &k0, int &k1) {
     const int par = prod_parity(d);
     const int nb = d.nb;
@@ -453,40 +459,60 @@ __device__ inline int cull_tile(const ProdDesc &d, int t, int lane, int &k0, int
     int32_t *out = d.kidx + (int64_t)t * nb;
     int base = 0;
     k0 = k1 = -1;
-    for (int kb = 0; kb < nb; kb += 64) {
-        const int k = kb + lane;
-        bool keep = false;
-        if (k < nb) {
-            const double prod = na[k] * nbt[k];
-            keep = !(prod < thr);
+    for (int kc = 0; kc < nb; kc += 64 * CULL_TU) {
+        double pa[CULL_TU], pb[CULL_TU];
+#pragma unroll
+        for (int u = 0; u < CULL_TU; ++u) {
+            const int k = kc + 64 * u + lane;
+            pa[u] = k < nb ? na[k] : 0.0;
+            pb[u] = k < nb ? nbt[k] : 0.0;
         }
-        const unsigned long long mask = __ballot(keep);
-        if (keep) out[base + __popcll(mask & ((1ull << lane) - 1ull))] = k;
-        if (base < 2 && mask) {  // wave-uniform
-            unsigned long long m = mask;
-            int f = base;
-            while (f < 2 && m) {
-                const int kk = kb + __ffsll((long long)m) - 1;
-                if (f == 0) k0 = kk; else k1 = kk;
-                m &= m - 1ull;
-                ++f;
+#pragma unroll
+        for (int u = 0; u < CULL_TU; ++u) {
+            const int kb = kc + 64 * u;
+            if (kb >= nb) break;  // wave-uniform
+            const int k = kb + lane;
+            const bool keep = k < nb && !(pa[u] * pb[u] < thr);
+            const unsigned long long mask = __ballot(keep);
+            if (keep) out[base + __popcll(mask & ((1ull << lane) - 1ull))] = k;
+            if (base < 2 && mask) {  // wave-uniform
+                unsigned long long m = mask;
+                int f = base;
+                while (f < 2 && m) {
+                    const int kk = kb + __ffsll((long long)m) - 1;
+                    if (f == 0) k0 = kk; else k1 = kk;
+                    m &= m - 1ull;
+                    ++f;
+                }
             }
+            base += __popcll(mask);
         }
-        base += __popcll(mask);
     }
     return base;
+}
+
+__global__ __launch_bounds__(256) void k_cull_tab(const ProdDesc *__restrict__ prods,
+                                                  const int32_t *__restrict__ pre, int nprod) {
+    const int p = find_slot(pre, nprod, blockIdx.x);
+    const ProdDesc &d = prods[p];
+    if (!prod_running(d)) return;
+    const int t = (blockIdx.x - pre[p]) * 4 + (threadIdx.x >> 6);
+    if (t >= d.nb * d.nb) return;
+    const int lane = threadIdx.x & 63;
+    int k0, k1;
+    const int cnt = cull_tile(d, t, lane, k0, k1);
+    if (lane == 0) d.cnt[t] = cnt;
 }
 
 template <typename T>
 using gptr = T __attribute__((address_space(1))) *;
 
-// Cull of the CULL_RI x CULL_J block of tiles (rows i0..i1-1, columns
+// Cull of a block of tiles (rows i0..i1-1, at most CULL_RI; columns
 // j0..j1-1) by one wave, for nb <= 64 * CULL_U: the leaf norms of the block's
-// CULL_RI rows of A stay in registers and B's columns come CULL_JG at a time,
-// all their loads issued together, so a wave waits one memory round trip per
-// CULL_JG columns (rather than one per 64 k of every tile) and reads each of
-// A's rows once for CULL_J tiles.  Lists, counts and order are those of
-// cull_tile.
+// rows of A stay in registers and B's columns come CULL_JG at a time, all
+// their loads issued together (the first group's with A's), so a wave waits
+// one memory round trip per CULL_JG columns and reads each of A's rows once
+// for CULL_J tiles.  Lists, counts and order are those of cull_tile.
 constexpr int CULL_U = 8, CULL_JG = 4;
 __device__ inline void cull_block_regs(const ProdDesc &d, int i0, int i1, int j0, int j1, int lane) {
     const int par = prod_parity(d);
@@ -496,28 +522,32 @@ __device__ inline void cull_block_regs(const ProdDesc &d, int i0, int i1, int j0
     const gptr<const double> nBt = (gptr<const double>)(d.nrmB[par] + (int64_t)nb * nb);  // ||B_kj|| at [j*nb + k]
     const gptr<int32_t> kidx = (gptr<int32_t>)d.kidx;
     const gptr<int32_t> cnt = (gptr<int32_t>)d.cnt;
-    double pa[CULL_RI][CULL_U];
+    double pa[CULL_RI][CULL_U], b[CULL_JG][CULL_U];
+    auto load_cols = [&](int jg) {
 #pragma unroll
-    for (int r = 0; r < CULL_RI; ++r)
+        for (int c = 0; c < CULL_JG; ++c) {
+            if (jg + c >= j1) break;  // wave-uniform
+#pragma unroll
+            for (int u = 0; u < CULL_U; ++u) {
+                const int k = 64 * u + lane;
+                b[c][u] = k < nb ? nBt[(int64_t)(jg + c) * nb + k] : 0.0;
+            }
+        }
+    };
+#pragma unroll
+    for (int r = 0; r < CULL_RI; ++r) {
+        if (i0 + r >= i1) break;  // wave-uniform
 #pragma unroll
         for (int u = 0; u < CULL_U; ++u) {
             const int k = 64 * u + lane;
-            pa[r][u] = (i0 + r < i1 && k < nb) ? nA[(int64_t)(i0 + r) * nb + k] : 0.0;
+            pa[r][u] = k < nb ? nA[(int64_t)(i0 + r) * nb + k] : 0.0;
         }
+    }
+    load_cols(j0);
     unsigned long long inb[CULL_U];  // lanes whose k = 64u + lane < nb
 #pragma unroll
     for (int u = 0; u < CULL_U; ++u) inb[u] = __builtin_amdgcn_ballot_w64(64 * u + lane < nb);
     for (int jg = j0; jg < j1; jg += CULL_JG) {
-        double b[CULL_JG][CULL_U];
-#pragma unroll
-        for (int c = 0; c < CULL_JG; ++c) {
-            const int j = min(jg + c, j1 - 1);  // past the block: a repeated column, not used
-#pragma unroll
-            for (int u = 0; u < CULL_U; ++u) {
-                const int k = 64 * u + lane;
-                b[c][u] = k < nb ? nBt[(int64_t)j * nb + k] : 0.0;
-            }
-        }
 #pragma unroll
         for (int c = 0; c < CULL_JG; ++c) {
             const int j = jg + c;
@@ -545,17 +575,18 @@ __device__ inline void cull_block_regs(const ProdDesc &d, int i0, int i1, int j0
                 if (lane == 0) cnt[t] = base;
             }
         }
+        if (jg + CULL_JG < j1) load_cols(jg + CULL_JG);
     }
 }
 
-__global__ __launch_bounds__(256) void k_cull_tab(const ProdDesc *__restrict__ prods,
+__global__ __launch_bounds__(256) void k_cull_blk(const ProdDesc *__restrict__ prods,
                                                   const int32_t *__restrict__ pre, int nprod) {
     const int p = find_slot(pre, nprod, blockIdx.x);
     const ProdDesc &d = prods[p];
     if (!prod_running(d)) return;
     const int nb = d.nb;
     const int wv = (blockIdx.x - pre[p]) * 4 + (threadIdx.x >> 6);
-    if (wv >= cull_waves(nb)) return;  // whole waves
+    if (wv >= cull_blk_waves(nb)) return;  // whole waves
     const int lane = threadIdx.x & 63;
     const int nbj = (nb + CULL_J - 1) / CULL_J;
     const int i0 = (wv / nbj) * CULL_RI, j0 = (wv % nbj) * CULL_J;
@@ -574,7 +605,10 @@ __global__ __launch_bounds__(256) void k_cull_tab(const ProdDesc *__restrict__ p
 }
 
 hipError_t launch_cull_tab(const ProdTable &t, hipStream_t st) {
-    hipLaunchKernelGGL(k_cull_tab, dim3(t.total_cull), dim3(256), 0, st, t.prods, t.cull_pre, t.nprod);
+    if (t.total_cull > 0)
+        hipLaunchKernelGGL(k_cull_tab, dim3(t.total_cull), dim3(256), 0, st, t.prods, t.cull_pre, t.nprod);
+    if (t.total_cullb > 0)
+        hipLaunchKernelGGL(k_cull_blk, dim3(t.total_cullb), dim3(256), 0, st, t.prods, t.cullb_pre, t.nprod);
     return hipGetLastError();
 }
 
