@@ -141,6 +141,27 @@ def test_batched_multiblock_sort_matches_solo(ctx):
         np.testing.assert_array_equal(host(Z), Zs)
 
 
+def test_batched_mixed_cull_kernels_match_solo(ctx):
+    """A 257 x 257-tile solve (the blocked cull, with ragged blocks at the
+    edge) shares its tables with two that take the per-tile cull; each kernel
+    covers only its own products.  All three must match their solo runs
+    bitwise."""
+    specs = [("kms", 8200, 0.8, 0, 1e-8), ("kms", 1100, 0.7, 1, 1e-8), ("kms", 300, 0.6, 2, 1e-6)]
+    mats = [make(k, n, p, sd) for (k, n, p, sd, _) in specs]
+    solos = [solo(ctx, s, 32, tau) for s, (_, _, _, _, tau) in zip(mats, specs)]
+    solves = [ctx.solve_begin(dev(s), tau, 1e-10, 30, leaf=32, stagnation_stop=True)
+              for s, (_, _, _, _, tau) in zip(mats, specs)]
+    steps = 0
+    while ctx.solve_step(solves, 3) > 0:
+        steps += 1
+        assert steps < 40
+    for sv, (Ys, Zs, infos) in zip(solves, solos):
+        Y, Z, info = sv.finish()
+        assert info["status"] == infos["status"] and info["iterations"] == infos["iterations"]
+        np.testing.assert_array_equal(host(Y), Ys)
+        np.testing.assert_array_equal(host(Z), Zs)
+
+
 def test_continuous_batching_join_and_leave(ctx):
     mats = [make(k, n, p, sd) for (k, n, p, sd, _, _) in CASES]
     solos = [solo(ctx, s, leaf, tau) for s, (_, _, _, _, leaf, tau) in zip(mats, CASES)]
