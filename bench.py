@@ -212,7 +212,9 @@ def run_batched(args):
                                                     for a, b in zip(infos, single_infos)),
         },
         "roofline": {"bound": "mfma", "kernel": "k_leaf_gemm", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": committed_traffic("batched_64_kms_gauss_n256-4096", prec),
+                     "traffic_unit": "bytes per launch (mean over the profiled pass)",
                      "launches": int(len(gemm_ms)), "avg_launch_ms": float(np.mean(gemm_ms)),
                      "timing": "separate profiled pass with plain launches"},
         "cpu_baseline": cpu,
