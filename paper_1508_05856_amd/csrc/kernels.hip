@@ -688,9 +688,14 @@ __device__ inline int xcd_slot(int idx, int count, int run) {
 }
 
 // Small tables (<= PLAN_ITEMS * 1024 tiles, the tables without hist_blocks):
-// every thread loads its items once, with independent loads, and keeps them
-// in registers for the histogram and the scatter.
+// every thread loads its items once, with independent loads, and keeps each
+// item's count and tile id packed in one register for the histogram and the
+// scatter.  That keeps the kernel under 48 registers, so its four waves per
+// SIMD fit where a single leaf-product workgroup (160 registers a wave) has
+// retired: on a GPU busy with other solves' leaf products the planner of a
+// solve is placed as soon as one of their workgroups ends.
 constexpr int PLAN_ITEMS = PLAN_SMALL_MAX / 1024;
+static_assert(PLAN_SMALL_MAX < (1 << 16), "tile ids and counts are packed in 16 bits each");
 
 __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict__ prods,
                                                      const int32_t *__restrict__ tile_pre,
@@ -700,22 +705,21 @@ __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict_
     extern __shared__ int hist[];  // max_nb + 1 bins
     const int total = tile_pre[nprod];
     for (int c = threadIdx.x; c <= max_nb; c += 1024) hist[c] = 0;
-    int cnt[PLAN_ITEMS], gid[PLAN_ITEMS];
+    unsigned it[PLAN_ITEMS];  // (count + 1) << 16 | tile id; 0 when the thread has no item there
 #pragma unroll
     for (int q = 0; q < PLAN_ITEMS; ++q) {
         const int g = threadIdx.x + q * 1024;
-        cnt[q] = -1;
-        gid[q] = 0;
+        it[q] = 0u;
         if (g < total) {
             int p, t;
-            cnt[q] = item_count(prods, tile_pre, morton, nprod, g, quad, p, t);
-            gid[q] = tile_pre[p] + t;
+            const int c = item_count(prods, tile_pre, morton, nprod, g, quad, p, t);
+            if (c >= 0) it[q] = ((unsigned)(c + 1) << 16) | (unsigned)(tile_pre[p] + t);
         }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PLAN_ITEMS; ++q)
-        if (cnt[q] >= 0) atomicAdd(&hist[cnt[q]], 1);
+        if (it[q]) atomicAdd(&hist[(int)(it[q] >> 16) - 1], 1);
     __syncthreads();
     if (threadIdx.x == 0) {
         int run = 0;
@@ -729,7 +733,7 @@ __global__ __launch_bounds__(1024) void k_plan_small(const ProdDesc *__restrict_
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PLAN_ITEMS; ++q)
-        if (cnt[q] >= 0) work[atomicAdd(&hist[cnt[q]], 1)] = gid[q];
+        if (it[q]) work[atomicAdd(&hist[(int)(it[q] >> 16) - 1], 1)] = (int)(it[q] & 0xffffu);
 }
 
 __device__ inline int bucket_of(int c) { return c < NBUCKET - 1 ? c : NBUCKET - 1; }
