@@ -160,19 +160,20 @@ def banded(n, seed, rate, width):
     return a
 
 
-@pytest.mark.parametrize("n", [8192, 8200])
-def test_multiply_cull_past_512_tiles_per_side_matches_oracle(ctx, n):
-    """Leaf 16 at nb = 512 (the cull's register-blocked path, every group of
-    64 k full) and nb = 513 (past it: the per-tile path, and a ragged last
-    tile of 8): the retained triple set equals the oracle's recursive cull
+@pytest.mark.parametrize("n,nb", [(4080, 255), (4096, 256), (8192, 512), (8200, 513)])
+def test_multiply_cull_kernels_at_their_bounds_match_oracle(ctx, n, nb):
+    """Leaf 16 at the cull kernels' bounds: nb = 255 (the last size of the
+    one-wave-per-tile kernel), nb = 256 (the first of the 4 x 16-tile blocks),
+    nb = 512 (the blocks' register path, every group of 64 k full) and
+    nb = 513 (past it: per-tile loops inside the blocks, and a ragged last
+    tile of 8).  The retained triple set equals the oracle's recursive cull
     (near-ties excluded) and the product is within 1e-13 of ||A|| ||B||."""
     leaf, tau = 16, 1e-7
     a = banded(n, 21, 0.02, 480)
     b = banded(n, 22, 0.02, 480)
     C, stats, trip = ctx.spamm_multiply(dev(a), dev(b), tau, leaf, triples=True)
     Co, Ro, cnt = oracle.spamm(a, b, leaf, tau)
-    nb = -(-n // leaf)
-    assert nb == (512 if n == 8192 else 513)
+    assert -(-n // leaf) == nb
     assert 0 < cnt < nb ** 3
     diff = set(map(tuple, host(trip).tolist())) ^ set(map(tuple, Ro.tolist()))
     if diff:  # only near-ties may differ
